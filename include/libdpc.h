@@ -1,0 +1,147 @@
+/*
+ * libdpc -- exact Density Peaks Clustering on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of "Faster Parallel Exact Density Peaks Clustering"
+ * (Huang, Yu, Shun).  Given n points in d dimensions and the three parameters
+ * d_cut, rho_min and delta_min (Section 3), it computes
+ *
+ *   rho[i]    the density of point i: the number of points j (i itself
+ *             included) with D(x_i, x_j) <= d_cut            (Definition 1);
+ *   dep[i]    the dependent point of i: the nearest point of strictly higher
+ *             priority, where the priority of j is the pair (rho[j], -j), so
+ *             that equal densities rank the lower index higher; an equal
+ *             distance is won by the smaller index            (Definition 2,
+ *             and the tie rule of the write-min in Section 5, Algorithm 2);
+ *   delta2[i] the squared dependent distance D(x_i, x_dep[i])^2
+ *                                                              (Definition 3);
+ *   label[i]  -1 for a noise point (rho < rho_min, Definition 4); otherwise
+ *             the index of the cluster centre (a non-noise point with
+ *             delta >= delta_min, Definition 5) reached by following
+ *             dependent points: the single-linkage step of Section 6.2,
+ *             Algorithm 3.
+ *
+ * D is the Euclidean distance.  Coordinates are int32, so D^2 is an integer
+ * and is computed exactly: D <= d_cut is decided as D^2 <= floor(d_cut^2)
+ * and delta >= delta_min as delta2 >= ceil(delta_min^2).  Every output is
+ * therefore a unique, exactly defined integer array.
+ *
+ * Sentinels: the point of highest priority has dep = -1 and
+ * delta2 = INT64_MAX (delta = infinity, Definition 3); so do points skipped as
+ * noise when dependents are requested only for rho >= rho_min.
+ *
+ * Conventions shared by every call below
+ *   - Array arguments are DEVICE pointers on the current HIP device.  points
+ *     is int32 [n][d], row-major and contiguous.  Outputs are allocated by the
+ *     caller and fully overwritten.  Indices are 0-based.
+ *   - n >= 0 and 1 <= d <= 8.  n = 0 is a no-op returning DPC_OK.  n must be
+ *     below 2^31.
+ *   - The sum over axes of (max - min)^2 of the coordinates must not exceed
+ *     2^63 - 1, so that every squared distance fits in int64; otherwise
+ *     DPC_ERR_RANGE.
+ *   - Work is enqueued on `stream` (0 = the null stream).  Calls that build
+ *     a spatial index read the coordinate bounds back to the host once, which
+ *     synchronises the stream at that point.  The library allocates its
+ *     workspace stream-ordered (hipMallocAsync) and releases it, also
+ *     stream-ordered, before returning; it keeps no pointer after return.
+ *     Outputs are ready when the stream's work completes.
+ *   - The return value is a dpc_status.  Argument errors are detected before
+ *     any GPU work is enqueued.  On any error the output contents are
+ *     unspecified.  Nothing aborts the process and no exception crosses the
+ *     interface.
+ *   - Results are bit-identical across runs, streams and tuning choices.
+ *     Concurrent calls on different streams are allowed.
+ */
+#ifndef LIBDPC_H
+#define LIBDPC_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#if defined(__GNUC__)
+#define DPC_API __attribute__((visibility("default")))
+#else
+#define DPC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DPC_OK = 0,
+    DPC_ERR_INVALID_ARG = 1, /* null pointer, n < 0, d outside [1, 8], NaN/negative d_cut, ... */
+    DPC_ERR_RANGE = 2,       /* squared distances could exceed int64 */
+    DPC_ERR_NOT_FOREST = 3,  /* dpc_cluster: a followed dependent edge does not rank higher */
+    DPC_ERR_OOM = 4,         /* workspace allocation failed */
+    DPC_ERR_HIP = 5          /* a HIP runtime call failed */
+} dpc_status;
+
+/* dpc_run flag: compute dependents only for points with rho >= rho_min, as
+ * Section 4.3, Algorithm 1 does; the others get (-1, INT64_MAX).  Labels do
+ * not change. */
+#define DPC_SKIP_NOISE_DEPENDENTS 1u
+
+/*
+ * Density (Section 3, Definition 1; Section 6.1 for the counting of whole
+ * index cells that lie inside the ball).
+ *   points  int32 [n][d] device, read only.
+ *   d_cut   radius >= 0 (may be +inf); NaN or negative -> DPC_ERR_INVALID_ARG.
+ *   rho     int32 [n] device, written: rho[i] >= 1.
+ */
+DPC_API int dpc_density(const int32_t *points, int64_t n, int32_t d, double d_cut,
+                int32_t *rho, hipStream_t stream);
+
+/*
+ * Dependent points (Section 3, Definitions 2-3; Section 4, the priority
+ * nearest-neighbour search of Algorithm 1).
+ *   rho      int32 [n] device, read only: any densities (typically from
+ *            dpc_density); they define the priority (rho[j], -j).
+ *   rho_min  0 computes every point; > 0 skips points with rho < rho_min,
+ *            which get (-1, INT64_MAX).  Negative -> DPC_ERR_INVALID_ARG.
+ *   dep      int32 [n] device, written.
+ *   delta2   int64 [n] device, written.
+ */
+DPC_API int dpc_dependent(const int32_t *points, int64_t n, int32_t d, const int32_t *rho,
+                  int32_t rho_min, int32_t *dep, int64_t *delta2, hipStream_t stream);
+
+/*
+ * Cluster labels (Section 3, Definitions 4-5 and the assignment rule after
+ * them; Section 6.2, Algorithm 3).  A non-noise point i with
+ * delta2[i] < ceil(delta_min^2) follows dep[i]; a non-noise point with
+ * delta2[i] >= ceil(delta_min^2) is a centre.  delta_min <= 0 makes every
+ * non-noise point a centre; +inf leaves only points with delta2 = INT64_MAX.
+ *   rho, dep, delta2  device arrays of n, read only (from the calls above or
+ *                     any caller data).
+ *   label             int32 [n] device, written.
+ * Every followed edge must lead to an index in [0, n) of strictly higher
+ * priority (which makes the graph a forest); otherwise DPC_ERR_NOT_FOREST.
+ * The check reads one flag back to the host, synchronising the stream.
+ */
+DPC_API int dpc_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2,
+                int32_t rho_min, double delta_min, int32_t *label, hipStream_t stream);
+
+/*
+ * The whole method: density, dependent points and labels, sharing one
+ * spatial index (the three steps of Section 1).  flags: 0 or
+ * DPC_SKIP_NOISE_DEPENDENTS.  Output arrays as above; all four are written.
+ */
+DPC_API int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,
+            double delta_min, uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2,
+            int32_t *label, hipStream_t stream);
+
+/* Static description of a status code; never NULL. */
+DPC_API const char *dpc_status_str(int status);
+
+/*
+ * Host-only helper: the integer threshold used for a radius r >= 0.
+ * round_up = 0 gives floor(r^2) (the d_cut rule), 1 gives ceil(r^2) (the
+ * delta_min rule), both saturating at INT64_MAX; r = +inf gives INT64_MAX.
+ * NaN, negative r or out == NULL -> DPC_ERR_INVALID_ARG.  No GPU work.
+ */
+DPC_API int dpc_square_threshold(double r, int32_t round_up, int64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBDPC_H */

@@ -1,0 +1,21 @@
+"""Exact Density Peaks Clustering on AMD Instinct MI355X (gfx950).
+
+The computation runs in libdpc, hand-written HIP behind the C interface of
+include/libdpc.h; this package is its thin Python binding.  See
+``_binding`` for the calls: ``density``, ``dependent``, ``cluster`` and
+``run`` take and return device tensors.
+"""
+from ._binding import (  # noqa: F401
+    DPCError,
+    EXPORTED,
+    INF,
+    LIB_PATH,
+    SKIP_NOISE_DEPENDENTS,
+    cluster,
+    density,
+    dependent,
+    load,
+    run,
+    square_threshold,
+    status_str,
+)

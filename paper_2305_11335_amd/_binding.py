@@ -1,0 +1,173 @@
+"""ctypes binding of libdpc (include/libdpc.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Tensors must live on the current ROCm device; PyTorch provides device memory
+and the stream handle.  There is no fallback: if libdpc.so is missing, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpc.so")
+
+OK, ERR_INVALID_ARG, ERR_RANGE, ERR_NOT_FOREST, ERR_OOM, ERR_HIP = range(6)
+SKIP_NOISE_DEPENDENTS = 1
+INF = (1 << 63) - 1
+
+EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_status_str",
+            "dpc_square_threshold")
+
+_lib = None
+
+
+class DPCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)} (status {status})")
+
+
+def load():
+    """Load libdpc.so (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i64, i32, u32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+    lib.dpc_density.argtypes = [P, i64, i32, dbl, P, P]
+    lib.dpc_density.restype = ctypes.c_int
+    lib.dpc_dependent.argtypes = [P, i64, i32, P, i32, P, P, P]
+    lib.dpc_dependent.restype = ctypes.c_int
+    lib.dpc_cluster.argtypes = [i64, P, P, P, i32, dbl, P, P]
+    lib.dpc_cluster.restype = ctypes.c_int
+    lib.dpc_run.argtypes = [P, i64, i32, dbl, i32, dbl, u32, P, P, P, P, P]
+    lib.dpc_run.restype = ctypes.c_int
+    lib.dpc_status_str.argtypes = [ctypes.c_int]
+    lib.dpc_status_str.restype = ctypes.c_char_p
+    lib.dpc_square_threshold.argtypes = [dbl, i32, P]
+    lib.dpc_square_threshold.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_str(status: int) -> str:
+    return load().dpc_status_str(int(status)).decode()
+
+
+def square_threshold(r: float, round_up: bool = False) -> int:
+    out = ctypes.c_int64(0)
+    st = load().dpc_square_threshold(float(r), int(bool(round_up)), ctypes.byref(out))
+    if st != OK:
+        raise DPCError(st, "dpc_square_threshold")
+    return out.value
+
+
+# ---------------------------------------------------------------------------
+# device calls
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _check_points(points):
+    torch = _torch()
+    if not isinstance(points, torch.Tensor) or not points.is_cuda:
+        raise TypeError("points must be a device tensor")
+    if points.dtype != torch.int32 or points.dim() != 2 or not points.is_contiguous():
+        raise TypeError("points must be a contiguous int32 [n, d] tensor")
+    return points.shape[0], points.shape[1]
+
+
+def _out(t, n, dtype, device):
+    torch = _torch()
+    if t is None:
+        return torch.empty(n, dtype=dtype, device=device)
+    if t.dtype != dtype or t.numel() != n or not t.is_contiguous() or t.device != device:
+        raise TypeError(f"output must be a contiguous {dtype} tensor of {n} elements on {device}")
+    return t
+
+
+def _vec(t, n, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or t.numel() != n \
+            or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} device tensor of {n} elements")
+    return t
+
+
+def density(points, d_cut: float, out=None, stream=None):
+    """rho (int32 [n]) for int32 [n, d] device points."""
+    torch = _torch()
+    n, d = _check_points(points)
+    rho = _out(out, n, torch.int32, points.device)
+    st = load().dpc_density(_ptr(points), n, d, float(d_cut), _ptr(rho), _stream(stream))
+    if st != OK:
+        raise DPCError(st, "dpc_density")
+    return rho
+
+
+def dependent(points, rho, rho_min: int = 0, dep=None, delta2=None, stream=None):
+    """(dep int32 [n], delta2 int64 [n]) for given densities."""
+    torch = _torch()
+    n, d = _check_points(points)
+    _vec(rho, n, torch.int32, "rho")
+    dep = _out(dep, n, torch.int32, points.device)
+    delta2 = _out(delta2, n, torch.int64, points.device)
+    st = load().dpc_dependent(_ptr(points), n, d, _ptr(rho), int(rho_min), _ptr(dep), _ptr(delta2),
+                              _stream(stream))
+    if st != OK:
+        raise DPCError(st, "dpc_dependent")
+    return dep, delta2
+
+
+def cluster(rho, dep, delta2, rho_min: int, delta_min: float, label=None, stream=None):
+    """label (int32 [n]): -1 for noise, else the index of the cluster centre."""
+    torch = _torch()
+    n = rho.numel()
+    _vec(rho, n, torch.int32, "rho")
+    _vec(dep, n, torch.int32, "dep")
+    _vec(delta2, n, torch.int64, "delta2")
+    label = _out(label, n, torch.int32, rho.device)
+    st = load().dpc_cluster(n, _ptr(rho), _ptr(dep), _ptr(delta2), int(rho_min), float(delta_min), _ptr(label),
+                            _stream(stream))
+    if st != OK:
+        raise DPCError(st, "dpc_cluster")
+    return label
+
+
+def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool = False, out=None,
+        stream=None):
+    """(rho, dep, delta2, label) of the whole method on device points."""
+    torch = _torch()
+    n, d = _check_points(points)
+    dev = points.device
+    if out is None:
+        out = (None, None, None, None)
+    rho = _out(out[0], n, torch.int32, dev)
+    dep = _out(out[1], n, torch.int32, dev)
+    delta2 = _out(out[2], n, torch.int64, dev)
+    label = _out(out[3], n, torch.int32, dev)
+    flags = SKIP_NOISE_DEPENDENTS if skip_noise else 0
+    st = load().dpc_run(_ptr(points), n, d, float(d_cut), int(rho_min), float(delta_min), flags, _ptr(rho),
+                        _ptr(dep), _ptr(delta2), _ptr(label), _stream(stream))
+    if st != OK:
+        raise DPCError(st, "dpc_run")
+    return rho, dep, delta2, label

@@ -1,0 +1,106 @@
+// Cluster labels (Section 3, Definitions 4-5; Section 6.2, Algorithm 3).
+//
+// Cutting every dependent edge with delta >= delta_min leaves a forest whose
+// trees are the clusters; the paper joins the kept edges with a concurrent
+// union-find.  Here every kept edge already points to a point of strictly
+// higher priority, so each tree's root is its centre and a label is found by
+// walking parent pointers up to the root.  Walks halve their path as they go
+// (a node's parent is replaced by its grandparent), so later walks are short.
+// Those writes race with other walks' reads, but every value ever stored in
+// parent[x] is an ancestor of x in the same tree, so any value read is a valid
+// step and every walk ends at the same root.
+#include "dpc_internal.hpp"
+
+namespace dpc {
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void k_flag_init(int32_t *flag) {
+    if (threadIdx.x == 0)
+        flag[0] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_parent(int64_t n, const int32_t *__restrict__ rho,
+                                                     const int32_t *__restrict__ dep,
+                                                     const int64_t *__restrict__ delta2, int32_t rho_min, int64_t Td,
+                                                     int validate, int32_t *__restrict__ par, int32_t *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int32_t r = rho[i];
+    int32_t p = (int32_t)i;
+    if (r >= rho_min && delta2[i] < Td) {
+        const int32_t j = dep[i];
+        bool ok = true;
+        if (validate) {
+            ok = j >= 0 && (int64_t)j < n;
+            if (ok) {
+                const int32_t rj = rho[j];
+                ok = rj > r || (rj == r && (int64_t)j < i);
+            }
+            if (!ok)
+                __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (ok)
+            p = j;
+    }
+    par[i] = p;
+}
+
+__global__ __launch_bounds__(kThreads) void k_roots(int64_t n, const int32_t *__restrict__ rho, int32_t rho_min,
+                                                    int32_t *par, int32_t *__restrict__ label, int32_t *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    if (rho[i] < rho_min) {
+        label[i] = -1;
+        return;
+    }
+    int32_t x = (int32_t)i;
+    // a chain of strictly rising priorities has fewer than n edges
+    for (int64_t steps = 0;; ++steps) {
+        if (steps > n) {
+            __hip_atomic_store(flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == x)
+            break;
+        const int32_t g = __hip_atomic_load(&par[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (g == p) {
+            x = p;
+            break;
+        }
+        __hip_atomic_store(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = g;
+    }
+    label[i] = x;
+}
+
+}  // namespace
+
+dpc_status launch_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2, int32_t rho_min,
+                          int64_t Td, bool validate, int32_t *label, Workspace &ws) {
+    hipStream_t s = ws.stream;
+    int32_t *par, *flag;
+    DPC_TRY(ws.alloc(&par, n));
+    DPC_TRY(ws.alloc(&flag, 1));
+    const dim3 grid(blocks_for(n, kThreads)), block(kThreads);
+    hipLaunchKernelGGL(k_flag_init, dim3(1), dim3(kWave), 0, s, flag);
+    hipLaunchKernelGGL(k_parent, grid, block, 0, s, n, rho, dep, delta2, rho_min, Td, validate ? 1 : 0, par, flag);
+    DPC_HIP(hipGetLastError());
+    if (validate) {
+        // an unchecked cycle would never let the walks end: check first
+        int32_t h = 0;
+        DPC_HIP(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
+        DPC_HIP(hipStreamSynchronize(s));
+        if (h != 0)
+            return DPC_ERR_NOT_FOREST;
+    }
+    hipLaunchKernelGGL(k_roots, grid, block, 0, s, n, rho, rho_min, par, label, flag);
+    DPC_HIP(hipGetLastError());
+    return DPC_OK;
+}
+
+}  // namespace dpc

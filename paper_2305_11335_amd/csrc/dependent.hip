@@ -1,0 +1,148 @@
+// Dependent points (Section 3, Definitions 2-3): for each query i, the
+// lexicographic minimum of (D^2(i, j), j) over the points j of strictly
+// higher priority (rho_j, -j).
+//
+// This is the priority nearest-neighbour query of Section 4.2.2: a node whose
+// highest key is not above the query's key holds no candidate and is pruned,
+// like any node whose box is farther than the best distance found so far.
+// A node at exactly the best distance is still visited, since it may hold an
+// equally near point of smaller index.  Each wavefront walks the tree with 64
+// consecutive sorted queries; the nearer child (for the first lane that still
+// needs the node) is visited first so the best distances shrink early.
+#include "traverse.hpp"
+
+#include <limits>
+
+namespace dpc {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename C, int D>
+__global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ coords, const C *__restrict__ box,
+                                                        const uint64_t *__restrict__ skey,
+                                                        const uint64_t *__restrict__ maxkey, int64_t n, int height,
+                                                        int32_t rho_min, const int32_t *__restrict__ sidx,
+                                                        int32_t *__restrict__ dep_out,
+                                                        int64_t *__restrict__ delta2_out) {
+    const int lane = __lane_id();
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q0 = q - lane;
+    if (q0 >= n)
+        return;
+    const bool valid = q < n;
+    const int64_t qq = valid ? q : q0;
+    C x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        x[k] = coords[qq * D + k];
+    const uint64_t kq = skey[qq];
+    const int32_t rho_q = (int32_t)((uint32_t)(kq >> 32) ^ 0x80000000u);
+    const bool active = valid && rho_q >= rho_min;
+
+    C best = std::numeric_limits<C>::max();
+    uint32_t best_low = 0;  // low key word of the best point; 0 = none yet
+    const uint32_t first_leaf = 1u << height;
+    uint32_t u = 1, v = 1;  // virtual (visit order) and real node index
+    int depth = 0;
+    for (;;) {
+        int64_t start, count;
+        node_range(v, depth, height, n, start, count);
+        bool descend = false;
+        uint32_t first_child = 0;
+        if (count > 0) {
+            bool want = false;
+            if (active && maxkey[v] > kq)
+                want = box_min_dist2<C, D>(x, box + (size_t)v * 2 * D) <= best;
+            if (v >= first_leaf) {
+                if (want) {
+                    for (int t = 0; t < (int)count; ++t) {
+                        const uint64_t kj = skey[start + t];
+                        if (kj > kq) {
+                            const C s = point_dist2<C, D>(x, coords + (start + t) * D);
+                            const uint32_t low = (uint32_t)kj;
+                            if (s < best || (s == best && low > best_low)) {
+                                best = s;
+                                best_low = low;
+                            }
+                        }
+                    }
+                }
+            } else {
+                const uint64_t m = __ballot(want);
+                if (m) {
+                    descend = true;
+                    const C *bl = box + (size_t)(2 * v) * 2 * D;
+                    const C dl = box_min_dist2<C, D>(x, bl);
+                    const C dr = box_min_dist2<C, D>(x, bl + 2 * D);
+                    const int leader = __ffsll((unsigned long long)m) - 1;
+                    first_child = (uint32_t)__builtin_amdgcn_readlane(dl <= dr ? 0 : 1, leader);
+                }
+            }
+        }
+        if (descend) {
+            u <<= 1;
+            v = (v << 1) | first_child;
+            ++depth;
+            continue;
+        }
+        while (u & 1u) {
+            u >>= 1;
+            v >>= 1;
+            --depth;
+        }
+        if (u == 0)
+            break;
+        u += 1;
+        v ^= 1u;
+    }
+    if (valid) {
+        const int32_t o = sidx[q];
+        if (best_low != 0) {
+            dep_out[o] = (int32_t)(0xFFFFFFFFu - best_low);
+            delta2_out[o] = (int64_t)best;
+        } else {
+            dep_out[o] = -1;
+            delta2_out[o] = std::numeric_limits<int64_t>::max();
+        }
+    }
+}
+
+template <typename C>
+dpc_status launch_typed(const Index &ix, int32_t rho_min, int32_t *dep, int64_t *delta2, hipStream_t s) {
+    const C *coords = static_cast<const C *>(ix.coords);
+    const C *box = static_cast<const C *>(ix.box);
+    const dim3 grid(blocks_for(ix.n, kThreads)), block(kThreads);
+    switch (ix.d) {
+#define DPC_DEP_CASE(DD)                                                                                        \
+    case DD:                                                                                                    \
+        hipLaunchKernelGGL((k_dependent<C, DD>), grid, block, 0, s, coords, box, ix.skey, ix.maxkey, ix.n,       \
+                           ix.height, rho_min, ix.sidx, dep, delta2);                                           \
+        break;
+        DPC_DEP_CASE(1)
+        DPC_DEP_CASE(2)
+        DPC_DEP_CASE(3)
+        DPC_DEP_CASE(4)
+        DPC_DEP_CASE(5)
+        DPC_DEP_CASE(6)
+        DPC_DEP_CASE(7)
+        DPC_DEP_CASE(8)
+#undef DPC_DEP_CASE
+    default:
+        return DPC_ERR_INVALID_ARG;
+    }
+    DPC_HIP(hipGetLastError());
+    return DPC_OK;
+}
+
+}  // namespace
+
+dpc_status launch_dependent(const Index &ix, const int32_t *srho, int32_t rho_min, int32_t *dep, int64_t *delta2,
+                            hipStream_t s) {
+    (void)srho;
+    if (ix.arith == Arith::F64)
+        return launch_typed<double>(ix, rho_min, dep, delta2, s);
+    return launch_typed<int64_t>(ix, rho_min, dep, delta2, s);
+}
+
+}  // namespace dpc

@@ -1,0 +1,120 @@
+// Internal declarations of libdpc (not installed; the public interface is
+// include/libdpc.h).
+//
+// The spatial index is a complete binary tree laid over the points sorted by
+// Morton code: leaf c holds sorted positions [c*LS, (c+1)*LS), node v (heap
+// numbering, root 1, children 2v and 2v+1) covers the union of its leaves and
+// stores its tight bounding box and the highest priority key below it.  It
+// plays the role of the paper's k-d trees: bounding boxes give the
+// containment count of Section 6.1 and the pruning of Section 3.2; the per
+// node maximum key gives the priority pruning of Section 4.2.2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/libdpc.h"
+
+namespace dpc {
+
+constexpr int kWave = 64;
+constexpr int kMaxDim = 8;
+constexpr int kLeafSize = 32;  // points per tree leaf
+
+// Coordinates and squared distances are exact in double when every squared
+// distance stays below 2^53 (the "f64" path); otherwise 64-bit integers.
+enum class Arith { F64, I64 };
+
+struct Index {
+    int64_t n = 0;
+    int d = 0;
+    Arith arith = Arith::F64;
+    int32_t lo[kMaxDim] = {0};
+    int32_t hi[kMaxDim] = {0};
+    int bits_per_dim = 0;   // Morton bits per axis
+    int shift = 0;          // coordinate quantisation shift before Morton coding
+    int height = 0;         // tree height: 2^height leaves
+    int64_t n_leaves = 0;   // 2^height
+    // device arrays (owned by the workspace)
+    void *coords = nullptr;     // sorted coordinates [n][d], double or int64
+    int32_t *sidx = nullptr;    // original index of each sorted position [n]
+    void *box = nullptr;        // node boxes [2*n_leaves][d][2] (min, max), like coords
+    uint64_t *skey = nullptr;   // priority key of each sorted position [n]
+    uint64_t *maxkey = nullptr; // per-node maximum key [2*n_leaves]
+};
+
+// Stream-ordered device workspace: every allocation is released together.
+struct Workspace {
+    hipStream_t stream;
+    void *ptrs[32];
+    int count = 0;
+    explicit Workspace(hipStream_t s) : stream(s) {}
+    ~Workspace() { release(); }
+    template <class T>
+    dpc_status alloc(T **out, size_t elems) {
+        *out = nullptr;
+        if (count >= 32)
+            return DPC_ERR_OOM;
+        void *p = nullptr;
+        size_t bytes = elems * sizeof(T);
+        if (bytes == 0)
+            bytes = 256;
+        if (hipMallocAsync(&p, bytes, stream) != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return DPC_ERR_OOM;
+        }
+        ptrs[count++] = p;
+        *out = static_cast<T *>(p);
+        return DPC_OK;
+    }
+    void release() {
+        for (int i = 0; i < count; ++i)
+            (void)hipFreeAsync(ptrs[i], stream);
+        count = 0;
+    }
+};
+
+#define DPC_HIP(call)                                      \
+    do {                                                   \
+        if ((call) != hipSuccess) {                        \
+            (void)hipGetLastError();                       \
+            return DPC_ERR_HIP;                            \
+        }                                                  \
+    } while (0)
+
+#define DPC_TRY(call)                                      \
+    do {                                                   \
+        dpc_status _st = (call);                           \
+        if (_st != DPC_OK)                                 \
+            return _st;                                    \
+    } while (0)
+
+// Exact thresholds (host).
+dpc_status square_threshold(double r, bool round_up, int64_t *out);
+
+// index.hip
+dpc_status build_index(const int32_t *points, int64_t n, int d, int64_t T, Workspace &ws, Index &ix);
+dpc_status build_priority(const int32_t *rho_sorted_or_null, const int32_t *rho_orig_or_null,
+                          Workspace &ws, Index &ix);
+
+// sort.hip: stable LSD radix sort of (key, value) pairs on the given key bits.
+dpc_status radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, Workspace &ws,
+                            uint64_t **keys_out, uint32_t **vals_out);
+
+// density.hip
+dpc_status launch_density(const Index &ix, int64_t T, int32_t *srho, int32_t *rho_out, hipStream_t s);
+
+// dependent.hip
+dpc_status launch_dependent(const Index &ix, const int32_t *srho_or_null, int32_t rho_min, int32_t *dep,
+                            int64_t *delta2, hipStream_t s);
+
+// cluster.hip
+dpc_status launch_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2,
+                          int32_t rho_min, int64_t Td, bool validate, int32_t *label, Workspace &ws);
+
+// Kernel-launch geometry helpers.
+inline unsigned blocks_for(int64_t items, int per_block) {
+    return static_cast<unsigned>((items + per_block - 1) / per_block);
+}
+
+}  // namespace dpc

@@ -1,0 +1,70 @@
+// Device helpers shared by the density and dependent-point kernels.
+//
+// Both kernels give one wavefront 64 consecutive sorted points as queries and
+// walk the implicit tree together: the walk is wave-uniform (node index and
+// depth live in scalar registers), and each lane keeps its own per-query
+// state.  The walk is stackless: in heap numbering the sibling of v is v ^ 1
+// and the parent v >> 1, so a depth-first order only needs the current node
+// and, when children may be visited in either order, a second "virtual"
+// index u whose low bit says whether v was the first or second child taken.
+#pragma once
+
+#include "dpc_internal.hpp"
+
+namespace dpc {
+
+// Squared distance from a point to a box (0 inside) and to the box's
+// farthest corner.  Exact for both coordinate types on the chosen path.
+template <typename C, int D>
+__device__ inline void box_dist2(const C (&x)[D], const C *__restrict__ b, C &dmin2, C &dmax2) {
+    C mn = 0, mx = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const C lo = b[2 * k], hi = b[2 * k + 1];
+        const C a = lo - x[k];
+        const C c = x[k] - hi;
+        C near = a > c ? a : c;
+        near = near > C(0) ? near : C(0);
+        const C far = -a > -c ? -a : -c;
+        mn += near * near;
+        mx += far * far;
+    }
+    dmin2 = mn;
+    dmax2 = mx;
+}
+
+template <typename C, int D>
+__device__ inline C box_min_dist2(const C (&x)[D], const C *__restrict__ b) {
+    C mn = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const C a = b[2 * k] - x[k];
+        const C c = x[k] - b[2 * k + 1];
+        C near = a > c ? a : c;
+        near = near > C(0) ? near : C(0);
+        mn += near * near;
+    }
+    return mn;
+}
+
+template <typename C, int D>
+__device__ inline C point_dist2(const C (&x)[D], const C *__restrict__ p) {
+    C s = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const C t = x[k] - p[k];
+        s += t * t;
+    }
+    return s;
+}
+
+// First sorted position and number of points below node v at `depth`.
+__device__ inline void node_range(uint32_t v, int depth, int height, int64_t n, int64_t &start, int64_t &count) {
+    const int sh = height - depth;
+    start = ((int64_t)(v - (1u << depth)) << sh) * kLeafSize;
+    const int64_t cap = (int64_t)kLeafSize << sh;
+    const int64_t left = n - start;
+    count = left < cap ? left : cap;
+}
+
+}  // namespace dpc

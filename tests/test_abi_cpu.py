@@ -1,0 +1,138 @@
+"""Host-side checks of libdpc that need no GPU.
+
+The library must load, export every call its header declares, convert radii
+to exact integer thresholds, and reject bad arguments before touching the
+device.  No call here enqueues GPU work.
+"""
+import ctypes
+import math
+import os
+import random
+import re
+import struct
+from fractions import Fraction
+
+import pytest
+
+import paper_2305_11335_amd as dpc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libdpc.h")
+INF = (1 << 63) - 1
+
+
+def _declared():
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"DPC_API\s+[\w\s\*]*?\b(dpc_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_interface():
+    assert _declared() == sorted(["dpc_cluster", "dpc_density", "dpc_dependent", "dpc_run",
+                                  "dpc_square_threshold", "dpc_status_str"])
+
+
+def test_library_exports_every_declared_symbol():
+    lib = dpc.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(dpc.EXPORTED) == _declared()
+
+
+def test_status_strings():
+    assert dpc.status_str(0) == "ok"
+    for s in range(1, 6):
+        assert dpc.status_str(s) and dpc.status_str(s) != "unknown status"
+    assert dpc.status_str(99) == "unknown status"
+
+
+def _exact(r, up):
+    if math.isinf(r):
+        return INF
+    v = Fraction(r) ** 2
+    return min(math.ceil(v) if up else math.floor(v), INF)
+
+
+BOUNDARY = [0.0, 5e-324, 0.5, 0.9999999999999999, 1.0, 1.0000000000000002, math.sqrt(2.0), 17.0, 51.0,
+            1500.0, 1500.0000000000002, 94906265.62425154, 94906265.62425156, 2.0 ** 26.5,
+            3037000499.0, 3037000499.97605, 3037000499.9760499, 3037000500.0, 2.0 ** 31.5, 1e20, math.inf]
+
+
+@pytest.mark.parametrize("r", BOUNDARY)
+def test_threshold_exact_at_boundaries(r):
+    assert dpc.square_threshold(r, False) == _exact(r, False)
+    assert dpc.square_threshold(r, True) == _exact(r, True)
+
+
+def test_threshold_exact_random():
+    rng = random.Random(7)
+    for _ in range(20000):
+        if rng.random() < 0.3:
+            bits = rng.getrandbits(64) & 0x7FEFFFFFFFFFFFFF
+            r = struct.unpack("<d", struct.pack("<Q", bits))[0]
+        else:
+            r = rng.uniform(0, 2.0 ** rng.randint(-3, 33))
+            if rng.random() < 0.3:
+                r = math.sqrt(float(rng.randint(0, 1 << 62)))
+        assert dpc.square_threshold(r, False) == _exact(r, False), r
+        assert dpc.square_threshold(r, True) == _exact(r, True), r
+
+
+def test_threshold_rejects_bad_radius():
+    for r in (-1.0, -0.0 - 1e-300, float("nan")):
+        with pytest.raises(dpc.DPCError):
+            dpc.square_threshold(r)
+    assert dpc.load().dpc_square_threshold(1.0, 0, None) == 1
+
+
+def _call(name, *args):
+    return getattr(dpc.load(), name)(*args)
+
+
+NULL = None
+
+
+def test_argument_errors_before_any_device_work():
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+    E = 1
+    assert _call("dpc_density", NULL, 5, 2, 1.0, fake, NULL) == E
+    assert _call("dpc_density", fake, 5, 2, 1.0, NULL, NULL) == E
+    assert _call("dpc_density", fake, -1, 2, 1.0, fake, NULL) == E
+    assert _call("dpc_density", fake, 5, 0, 1.0, fake, NULL) == E
+    assert _call("dpc_density", fake, 5, 9, 1.0, fake, NULL) == E
+    assert _call("dpc_density", fake, 5, 2, float("nan"), fake, NULL) == E
+    assert _call("dpc_density", fake, 5, 2, -1.0, fake, NULL) == E
+    assert _call("dpc_density", fake, 1 << 31, 2, 1.0, fake, NULL) == E
+    assert _call("dpc_dependent", fake, 5, 2, fake, -1, fake, fake, NULL) == E
+    assert _call("dpc_dependent", fake, 5, 2, NULL, 0, fake, fake, NULL) == E
+    assert _call("dpc_dependent", fake, 5, 2, fake, 0, fake, NULL, NULL) == E
+    assert _call("dpc_cluster", 5, fake, fake, fake, -1, 1.0, fake, NULL) == E
+    assert _call("dpc_cluster", 5, fake, fake, fake, 0, float("nan"), fake, NULL) == E
+    assert _call("dpc_cluster", 5, fake, NULL, fake, 0, 1.0, fake, NULL) == E
+    assert _call("dpc_cluster", -2, fake, fake, fake, 0, 1.0, fake, NULL) == E
+    assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 2, fake, fake, fake, fake, NULL) == E
+    assert _call("dpc_run", fake, 5, 2, 1.0, -3, 1.0, 0, fake, fake, fake, fake, NULL) == E
+    assert _call("dpc_run", fake, 5, 2, 1.0, 0, float("nan"), 0, fake, fake, fake, fake, NULL) == E
+    assert _call("dpc_run", fake, 5, 2, float("nan"), 0, 1.0, 0, fake, fake, fake, fake, NULL) == E
+    assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 0, fake, fake, NULL, fake, NULL) == E
+    assert _call("dpc_run", fake, 5, 0, 1.0, 0, 1.0, 0, fake, fake, fake, fake, NULL) == E
+
+
+def test_empty_input_is_a_no_op():
+    assert _call("dpc_density", NULL, 0, 2, 1.0, NULL, NULL) == 0
+    assert _call("dpc_dependent", NULL, 0, 3, NULL, 0, NULL, NULL, NULL) == 0
+    assert _call("dpc_cluster", 0, NULL, NULL, NULL, 0, 1.0, NULL, NULL) == 0
+    assert _call("dpc_run", NULL, 0, 8, 1.0, 0, 1.0, 1, NULL, NULL, NULL, NULL, NULL) == 0
+
+
+def test_product_path_has_no_oracle_or_fallback():
+    # The library package must not reach the oracle, and must fail loudly when
+    # its shared library is missing rather than compute anything elsewhere.
+    pkg = os.path.join(ROOT, "paper_2305_11335_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                with open(os.path.join(dirpath, f)) as fh:
+                    src = fh.read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+                assert "dpc_oracle" not in src, f

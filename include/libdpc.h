@@ -41,9 +41,11 @@
  *   - Work is enqueued on `stream` (0 = the null stream).  Calls that build
  *     a spatial index read the coordinate bounds back to the host once, which
  *     synchronises the stream at that point.  The library allocates its
- *     workspace stream-ordered (hipMallocAsync) and releases it, also
- *     stream-ordered, before returning; it keeps no pointer after return.
- *     Outputs are ready when the stream's work completes.
+ *     workspace stream-ordered from a memory pool of its own on the current
+ *     device and releases it, also stream-ordered, before returning; it keeps
+ *     no pointer to caller memory after return.  The pool keeps freed memory
+ *     for later calls (up to the largest workspace used) until the process
+ *     ends.  Outputs are ready when the stream's work completes.
  *   - The return value is a dpc_status.  Argument errors are detected before
  *     any GPU work is enqueued.  On any error the output contents are
  *     unspecified.  Nothing aborts the process and no exception crosses the

@@ -72,11 +72,14 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                 const uint64_t m = __ballot(want);
                 if (m) {
                     descend = true;
-                    const C *bl = box + (size_t)(2 * v) * 2 * D;
-                    const C dl = box_min_dist2<C, D>(x, bl);
-                    const C dr = box_min_dist2<C, D>(x, bl + 2 * D);
-                    const int leader = __ffsll((unsigned long long)m) - 1;
-                    first_child = (uint32_t)__builtin_amdgcn_readlane(dl <= dr ? 0 : 1, leader);
+                    // the left child is never empty; the right one may be
+                    if (count > ((int64_t)kLeafSize << (height - depth - 1))) {
+                        const C *bl = box + (size_t)(2 * v) * 2 * D;
+                        const C dl = box_min_dist2<C, D>(x, bl);
+                        const C dr = box_min_dist2<C, D>(x, bl + 2 * D);
+                        const int leader = __ffsll((unsigned long long)m) - 1;
+                        first_child = (uint32_t)__builtin_amdgcn_readlane(dl <= dr ? 0 : 1, leader);
+                    }
                 }
             }
         }

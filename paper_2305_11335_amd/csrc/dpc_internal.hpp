@@ -1,13 +1,13 @@
 // Internal declarations of libdpc (not installed; the public interface is
 // include/libdpc.h).
 //
-// The spatial index is a complete binary tree laid over the points sorted by
-// Morton code: leaf c holds sorted positions [c*LS, (c+1)*LS), node v (heap
-// numbering, root 1, children 2v and 2v+1) covers the union of its leaves and
-// stores its tight bounding box and the highest priority key below it.  It
-// plays the role of the paper's k-d trees: bounding boxes give the
-// containment count of Section 6.1 and the pruning of Section 3.2; the per
-// node maximum key gives the priority pruning of Section 4.2.2.
+// The spatial index is a balanced k-d tree in an implicit layout: the points
+// are permuted so that leaf c holds positions [c*LS, (c+1)*LS) and node v
+// (heap numbering, root 1, children 2v and 2v+1) covers the union of its
+// leaves; each node's points are split evenly across the longest side of its
+// box.  Nodes store their tight bounding box and the highest priority key
+// below them: the boxes give the containment count of Section 6.1 and the
+// pruning of Section 3.2, the keys the priority pruning of Section 4.2.2.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,8 +31,6 @@ struct Index {
     Arith arith = Arith::F64;
     int32_t lo[kMaxDim] = {0};
     int32_t hi[kMaxDim] = {0};
-    int bits_per_dim = 0;   // Morton bits per axis
-    int shift = 0;          // coordinate quantisation shift before Morton coding
     int height = 0;         // tree height: 2^height leaves
     int64_t n_leaves = 0;   // 2^height
     // device arrays (owned by the workspace)
@@ -43,23 +41,32 @@ struct Index {
     uint64_t *maxkey = nullptr; // per-node maximum key [2*n_leaves]
 };
 
+// The library's stream-ordered memory pool on the current device (created on
+// first use).  Unlike the device's default pool it keeps freed memory
+// instead of returning it at every synchronisation, so repeated calls do not
+// map their workspace again.  Returns nullptr if no pool could be created.
+hipMemPool_t workspace_pool();
+
 // Stream-ordered device workspace: every allocation is released together.
 struct Workspace {
     hipStream_t stream;
-    void *ptrs[32];
+    static constexpr int kCap = 128;
+    void *ptrs[kCap];
     int count = 0;
-    explicit Workspace(hipStream_t s) : stream(s) {}
+    hipMemPool_t pool;
+    explicit Workspace(hipStream_t s) : stream(s), pool(workspace_pool()) {}
     ~Workspace() { release(); }
     template <class T>
     dpc_status alloc(T **out, size_t elems) {
         *out = nullptr;
-        if (count >= 32)
+        if (count >= kCap)
             return DPC_ERR_OOM;
         void *p = nullptr;
         size_t bytes = elems * sizeof(T);
         if (bytes == 0)
             bytes = 256;
-        if (hipMallocAsync(&p, bytes, stream) != hipSuccess || p == nullptr) {
+        const hipError_t e = pool ? hipMallocFromPoolAsync(&p, bytes, pool, stream) : hipMallocAsync(&p, bytes, stream);
+        if (e != hipSuccess || p == nullptr) {
             (void)hipGetLastError();
             return DPC_ERR_OOM;
         }
@@ -97,9 +104,9 @@ dpc_status build_index(const int32_t *points, int64_t n, int d, int64_t T, Works
 dpc_status build_priority(const int32_t *rho_sorted_or_null, const int32_t *rho_orig_or_null,
                           Workspace &ws, Index &ix);
 
-// sort.hip: stable LSD radix sort of (key, value) pairs on the given key bits.
-dpc_status radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, Workspace &ws,
-                            uint64_t **keys_out, uint32_t **vals_out);
+// kdtree.hip: the balanced k-d tree over ix.n points (ix.lo/hi/height/arith
+// set); fills ix.coords, ix.sidx and ix.box.
+dpc_status build_kdtree(const int32_t *points, Workspace &ws, Index &ix);
 
 // density.hip
 dpc_status launch_density(const Index &ix, int64_t T, int32_t *srho, int32_t *rho_out, hipStream_t s);

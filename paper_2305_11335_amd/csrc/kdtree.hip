@@ -7,16 +7,19 @@
 // share a level.  Points live in structure-of-arrays form (coordinate minus
 // the global minimum, as uint32, plus the id).  A node's median along its
 // split axis is found exactly by most-significant-digit radix select: each
-// pass histograms one 8-bit digit of the points that still match the digits
-// found so far.  The node is then partitioned stably: "less than the median"
-// and "equal to the median" flags are scanned, and the first equal points in
-// array order fill the left half.  The same pass reduces the children's boxes.
+// pass histograms one digit of the points that still match the digits found
+// so far (11-bit digits while a level has few nodes, 8-bit below).  The node
+// is then partitioned stably: "less than the median" and "equal to the
+// median" flags are scanned, and the first equal points in array order fill
+// the left half.  The same pass reduces the children's boxes.
 //
 // Bottom levels: one workgroup owns a subtree of at most 2048 (d <= 3) or
-// 1024 points, keeps it in LDS and, level by level, sorts every node's points
-// along that node's split axis with a bitonic network; the first half of each
-// sorted node is its left child.  It writes the subtree's boxes, coordinates
-// and ids straight into the final arrays.
+// 1024 points and keeps it in LDS.  On each level every wavefront takes whole
+// nodes: it finds the node's median by radix select over a wave-private
+// histogram and computes every point's destination with a stable ballot
+// scan; the workgroup then permutes the subtree through registers.  It
+// writes the subtree's boxes, coordinates and ids straight into the final
+// arrays.
 //
 // Every 2048-point tile of the top levels lies inside a single node, because
 // node sizes there are multiples of the tile.
@@ -32,22 +35,30 @@ constexpr int kWaves = kThreads / kWave;
 constexpr int kTile = 2048;
 constexpr int kItems = kTile / kThreads;    // 8
 constexpr int kWaveItems = kItems * kWave;  // 512
-constexpr int kDigits = 8;
-constexpr int kBins = 1 << kDigits;
-constexpr int kMaxPasses = 4;  // 32-bit extents
-static_assert(kThreads == kBins, "one thread per bin");
+
+template <int BITS>
+struct Digit {
+    static constexpr int kBits = BITS;
+    static constexpr int kBins = 1 << BITS;
+    static constexpr int kPerThread = kBins / kThreads;
+    static_assert(kPerThread >= 1, "at least one bin per thread");
+};
 
 template <int D>
 struct Bottom {
-    // points per bottom subtree: what fits in LDS together with the sort keys
+    // points per bottom subtree: what fits in LDS next to the scratch arrays
     static constexpr int kSize = D <= 3 ? 2048 : 1024;
-    static constexpr int kLevels = D <= 3 ? 6 : 5;  // log2(kSize / kLeafSize)
+    static constexpr int kLevels = D <= 3 ? 6 : 5;    // log2(kSize / kLeafSize)
     static constexpr int kNodes = kSize / kLeafSize;  // most nodes on one level
     static_assert((kLeafSize << kLevels) == kSize, "subtree size");
 };
 
 struct Origin {
     int32_t v[kMaxDim];  // global coordinate minimum per axis
+};
+
+struct Spans {
+    uint32_t v[kMaxDim];  // max - min per axis
 };
 
 __device__ inline uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
@@ -95,6 +106,27 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
+// Orders the LDS accesses of the lanes of one wavefront: everything a lane
+// did before is visible to every lane of the wave after.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lanes (among `valid` ones) whose NBITS-bit digit equals this lane's.
+template <int NBITS>
+__device__ inline uint64_t match_digit(uint32_t dg, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < NBITS; ++b) {
+        const bool bit = (dg >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
 // Longest side of a box given as [D][lo, hi] relative coordinates; the lowest
 // axis wins a tie.
 template <int D>
@@ -131,15 +163,15 @@ __device__ inline NodeGeom node_geom(int64_t t, int64_t S, int64_t n) {
 struct NodeSelect {
     int axis;
     uint32_t base;  // the box minimum along the axis; select works on x - base
-    int passes;     // 8-bit digits of the axis extent
+    int passes;     // digits of the axis extent
 };
 
-template <int D>
+template <int D, int BITS>
 __device__ inline NodeSelect node_select(const uint32_t *__restrict__ nbox) {
     NodeSelect s;
     s.axis = longest_axis<D>(nbox);
     s.base = nbox[2 * s.axis];
-    s.passes = (int)((bit_length(nbox[2 * s.axis + 1] - s.base) + kDigits - 1) / kDigits);
+    s.passes = (int)((bit_length(nbox[2 * s.axis + 1] - s.base) + BITS - 1) / BITS);
     return s;
 }
 
@@ -151,32 +183,45 @@ struct SelectState {
     uint32_t prefix, less, rank;
 };
 
+template <int BITS>
 __device__ inline SelectState replay(const uint32_t *__restrict__ hist_node, int64_t pass_stride, int upto,
                                      uint32_t half, uint32_t *s_w, uint32_t *s_pick) {
+    using Dg = Digit<BITS>;
     SelectState st{0u, 0u, half};
     for (int p = 0; p < upto; ++p) {
-        const uint32_t c = hist_node[(int64_t)p * pass_stride + threadIdx.x];
-        const uint32_t incl = block_incl_scan(c, s_w);
-        const uint32_t excl = incl - c;
-        if (excl <= st.rank && st.rank < incl) {
-            s_pick[0] = threadIdx.x;
-            s_pick[1] = excl;
+        const uint32_t *hp = hist_node + (int64_t)p * pass_stride + threadIdx.x * Dg::kPerThread;
+        uint32_t c[Dg::kPerThread];
+        uint32_t mine = 0;
+#pragma unroll
+        for (int b = 0; b < Dg::kPerThread; ++b) {
+            c[b] = hp[b];
+            mine += c[b];
+        }
+        uint32_t cum = block_incl_scan(mine, s_w) - mine;
+#pragma unroll
+        for (int b = 0; b < Dg::kPerThread; ++b) {
+            if (cum <= st.rank && st.rank < cum + c[b]) {
+                s_pick[0] = threadIdx.x * Dg::kPerThread + b;
+                s_pick[1] = cum;
+            }
+            cum += c[b];
         }
         __syncthreads();
         const uint32_t dg = s_pick[0], below = s_pick[1];
         __syncthreads();
-        st.prefix = (st.prefix << kDigits) | dg;
+        st.prefix = (st.prefix << BITS) | dg;
         st.less += below;
         st.rank -= below;
     }
     return st;
 }
 
-template <int D>
+template <int D, int BITS>
 __global__ __launch_bounds__(kThreads) void k_sel_hist(const uint32_t *__restrict__ X, int64_t n, int j, int h,
                                                        const uint32_t *__restrict__ boxes, uint32_t *__restrict__ hist,
                                                        int pass) {
-    __shared__ uint32_t s_h[kBins];
+    using Dg = Digit<BITS>;
+    __shared__ uint32_t s_h[Dg::kBins];
     __shared__ uint32_t s_w[kWaves];
     __shared__ uint32_t s_pick[2];
     const int64_t e0 = (int64_t)blockIdx.x * kTile;
@@ -185,29 +230,38 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const uint32_t *__restric
     const int64_t S = (int64_t)kLeafSize << (h - j);
     const int64_t t = e0 / S;
     const NodeGeom g = node_geom(t, S, n);
-    const NodeSelect ns = node_select<D>(boxes + t * 2 * D);
+    const NodeSelect ns = node_select<D, BITS>(boxes + t * 2 * D);
     if (pass >= ns.passes || g.half == g.count)
         return;  // this node's median is already known (or it has no right half)
-    const int64_t pass_stride = (1ll << j) * kBins;
-    const SelectState st = replay(hist + t * kBins, pass_stride, pass, (uint32_t)g.half, s_w, s_pick);
-    const int shift = (ns.passes - 1 - pass) * kDigits;
-    s_h[threadIdx.x] = 0;
+    const int64_t pass_stride = (1ll << j) * Dg::kBins;
+    const SelectState st = replay<BITS>(hist + t * Dg::kBins, pass_stride, pass, (uint32_t)g.half, s_w, s_pick);
+    const int shift = (ns.passes - 1 - pass) * BITS;
+    for (int b = threadIdx.x; b < Dg::kBins; b += kThreads)
+        s_h[b] = 0;
     __syncthreads();
     const uint32_t *x = X + (int64_t)ns.axis * n;
     const int w = threadIdx.x / kWave;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const int64_t e = e0 + (int64_t)w * kWaveItems + (int64_t)r * kWave + __lane_id();
+        bool match = false;
+        uint32_t dg = 0;
         if (e < n) {
             const uint64_t v = (uint64_t)(x[e] - ns.base);
-            if ((v >> (shift + kDigits)) == (uint64_t)st.prefix)
-                atomicAdd(&s_h[(uint32_t)(v >> shift) & (kBins - 1)], 1u);
+            match = (v >> (shift + BITS)) == (uint64_t)st.prefix;
+            dg = (uint32_t)(v >> shift) & (Dg::kBins - 1);
         }
+        // one LDS update per distinct digit in the wave
+        const uint64_t peers = match_digit<BITS>(dg, match);
+        if (match && (peers & lanes_below()) == 0)
+            atomicAdd(&s_h[dg], (uint32_t)__popcll(peers));
     }
     __syncthreads();
-    const uint32_t c = s_h[threadIdx.x];
-    if (c)
-        atomicAdd(&hist[(int64_t)pass * pass_stride + t * kBins + threadIdx.x], c);
+    for (int b = threadIdx.x; b < Dg::kBins; b += kThreads) {
+        const uint32_t c = s_h[b];
+        if (c)
+            atomicAdd(&hist[(int64_t)pass * pass_stride + t * Dg::kBins + b], c);
+    }
 }
 
 struct NodeSplit {
@@ -218,13 +272,14 @@ struct NodeSplit {
     int32_t all_left;  // the node has no right half
 };
 
-template <typename C, int D>
+template <typename C, int D, int BITS>
 __global__ __launch_bounds__(kThreads) void k_part_count(const uint32_t *__restrict__ X, int64_t n, int j, int h,
                                                          const uint32_t *__restrict__ boxes,
                                                          uint32_t *__restrict__ child_boxes,
                                                          const uint32_t *__restrict__ hist, NodeSplit *__restrict__ split,
                                                          uint32_t *__restrict__ cnt_less, uint32_t *__restrict__ cnt_eq,
                                                          C *__restrict__ tree_box, Origin origin) {
+    using Dg = Digit<BITS>;
     __shared__ uint32_t s_w[kWaves];
     __shared__ uint32_t s_pick[2];
     __shared__ uint32_t s_c[2][kWaves];
@@ -235,11 +290,11 @@ __global__ __launch_bounds__(kThreads) void k_part_count(const uint32_t *__restr
     const int64_t t = e0 / S;
     const NodeGeom g = node_geom(t, S, n);
     const uint32_t *nb = boxes + t * 2 * D;
-    const NodeSelect ns = node_select<D>(nb);
+    const NodeSelect ns = node_select<D, BITS>(nb);
     const bool all_left = g.half == g.count;
     SelectState st{0u, 0u, 0u};
     if (!all_left)
-        st = replay(hist + t * kBins, (1ll << j) * kBins, ns.passes, (uint32_t)g.half, s_w, s_pick);
+        st = replay<BITS>(hist + t * Dg::kBins, (1ll << j) * Dg::kBins, ns.passes, (uint32_t)g.half, s_w, s_pick);
     // with every digit chosen, prefix is the exact median and rank its rank
     // among the points equal to it
     if (e0 == g.start && threadIdx.x == 0) {
@@ -375,7 +430,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(const uint32_t *__res
         off_l += s_w[0][q];
         off_e += s_w[1][q];
     }
-    // local box accumulators of the two children (L: left, R: right)
+    // box accumulators of the two children (l: left, r: right)
     uint32_t lmin[D], lmax[D], rmin[D], rmax[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -440,10 +495,6 @@ __global__ void k_fill_u32(uint32_t *__restrict__ a, int64_t m, uint32_t v) {
         a[i] = v;
 }
 
-struct Spans {
-    uint32_t v[kMaxDim];  // max - min per axis
-};
-
 // the root's box in relative coordinates: [0, span] on every axis
 template <int D>
 __global__ void k_root_box(uint32_t *__restrict__ nb, Spans spans) {
@@ -476,12 +527,14 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
     constexpr int M = Bottom<D>::kSize;
     constexpr int NB = Bottom<D>::kNodes;
     constexpr int PER = M / kThreads;
+    constexpr int kB = 8;  // digit bits of the in-LDS select
+    constexpr int kNB = 1 << kB;
+    constexpr int kLaneBins = kNB / kWave;  // 4
     __shared__ uint32_t s_x[D][M];
     __shared__ uint32_t s_id[M];
-    __shared__ uint64_t s_key[M];
-    __shared__ uint16_t s_slot[M];
+    __shared__ uint16_t s_dst[M];
+    __shared__ uint32_t s_hist[kWaves][kNB];
     __shared__ uint32_t s_box[NB][D][2];
-    __shared__ uint8_t s_axis[NB];
 
     const int64_t S0 = (int64_t)kLeafSize << (h - jb);  // at most M
     const int64_t s0 = (int64_t)blockIdx.x * S0;
@@ -495,6 +548,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
         s_id[i] = I[s0 + i];
     }
     const int w = threadIdx.x / kWave;
+    const int lane = __lane_id();
     for (int l = jb; l <= h; ++l) {
         const int S = kLeafSize << (h - l);  // node size on this level
         const int nsub = (cnt0 + S - 1) / S;
@@ -507,7 +561,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
         __syncthreads();
         // boxes: every 32-point group lies inside one node (S >= 32)
         for (int base = w * kWave; base < cnt0; base += kThreads) {
-            const int i = base + __lane_id();
+            const int i = base + lane;
             const bool have = i < cnt0;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
@@ -519,7 +573,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
                     a = ta < a ? ta : a;
                     b = tb > b ? tb : b;
                 }
-                if ((i & (kLeafSize - 1)) == 0 && i < cnt0) {
+                if ((i & (kLeafSize - 1)) == 0 && have) {
                     atomicMin(&s_box[i / S][k][0], a);
                     atomicMax(&s_box[i / S][k][1], b);
                 }
@@ -533,55 +587,106 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
                 tree_box[(v * D + k) * 2 + 0] = (C)((int64_t)origin.v[k] + (int64_t)s_box[u][k][0]);
                 tree_box[(v * D + k) * 2 + 1] = (C)((int64_t)origin.v[k] + (int64_t)s_box[u][k][1]);
             }
-            s_axis[u] = (uint8_t)longest_axis<D>(&s_box[u][0][0]);
         }
         if (l == h)
             break;
-        __syncthreads();
-        // sort keys: node index, then the coordinate along the node's axis
-        // relative to its box; padding sorts last within the last node
-        const int len = nsub * S;
-        for (int i = threadIdx.x; i < len; i += kThreads) {
-            const int u = i / S;
-            uint64_t key = ((uint64_t)u << 34) | 0x1FFFFFFFFull;
-            if (i < cnt0) {
-                const int a = s_axis[u];
-                key = ((uint64_t)u << 34) | ((uint64_t)(s_x[a][i] - s_box[u][a][0]) << 1);
+        // each wave splits whole nodes: exact median, then stable destinations
+        for (int u = w; u < nsub; u += kWaves) {
+            const int base = u * S;
+            const int cnt = cnt0 - base < S ? cnt0 - base : S;
+            const int half = cnt < S / 2 ? cnt : S / 2;
+            if (half == cnt) {
+                for (int i = lane; i < cnt; i += kWave)
+                    s_dst[base + i] = (uint16_t)(base + i);
+                continue;
             }
-            s_key[i] = key;
-            s_slot[i] = (uint16_t)i;
-        }
-        __syncthreads();
-        // bitonic sort of every node (length S, a power of two)
-        for (int size = 2; size <= S; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int q = threadIdx.x; q < len / 2; q += kThreads) {
-                    const int i = (q / stride) * 2 * stride + (q % stride);
-                    const int k2 = i + stride;
-                    const bool asc = ((i & (S - 1)) & size) == 0;
-                    const uint64_t a = s_key[i], b = s_key[k2];
-                    if ((a > b) == asc) {
-                        s_key[i] = b;
-                        s_key[k2] = a;
-                        const uint16_t t = s_slot[i];
-                        s_slot[i] = s_slot[k2];
-                        s_slot[k2] = t;
-                    }
+            const int a = longest_axis<D>(&s_box[u][0][0]);
+            const uint32_t lo = s_box[u][a][0];
+            const int passes = (int)((bit_length(s_box[u][a][1] - lo) + kB - 1) / kB);
+            uint32_t prefix = 0, rank = (uint32_t)half;
+            for (int p = 0; p < passes; ++p) {
+                const int shift = (passes - 1 - p) * kB;
+                // The histogram is shared by the lanes of this wave: every
+                // access is atomic and the phases are fenced at wavefront
+                // scope, so no lane's own store can stand in for what the
+                // other lanes added.
+#pragma unroll
+                for (int b = 0; b < kLaneBins; ++b)
+                    __hip_atomic_store(&s_hist[w][lane * kLaneBins + b], 0u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+                wave_sync();
+                for (int i = lane; i < cnt; i += kWave) {
+                    const uint64_t v = (uint64_t)(s_x[a][base + i] - lo);
+                    if ((v >> (shift + kB)) == (uint64_t)prefix)
+                        __hip_atomic_fetch_add(&s_hist[w][(uint32_t)(v >> shift) & (kNB - 1)], 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WAVEFRONT);
                 }
-                __syncthreads();
+                wave_sync();
+                // lane owns bins [4*lane, 4*lane + 4)
+                uint32_t c[kLaneBins];
+                uint32_t mine = 0;
+#pragma unroll
+                for (int b = 0; b < kLaneBins; ++b) {
+                    c[b] = __hip_atomic_load(&s_hist[w][lane * kLaneBins + b], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    mine += c[b];
+                }
+                wave_sync();
+                uint32_t cum = wave_incl_scan(mine) - mine;
+                uint32_t pick = 0, below = 0;
+                bool found = false;
+#pragma unroll
+                for (int b = 0; b < kLaneBins; ++b) {
+                    if (cum <= rank && rank < cum + c[b]) {
+                        pick = (uint32_t)(lane * kLaneBins + b);
+                        below = cum;
+                        found = true;
+                    }
+                    cum += c[b];
+                }
+                const uint64_t fm = __ballot(found);
+                const int src = __ffsll((unsigned long long)fm) - 1;
+                pick = (uint32_t)__builtin_amdgcn_readlane((int)pick, src);
+                below = (uint32_t)__builtin_amdgcn_readlane((int)below, src);
+                prefix = (prefix << kB) | pick;
+                rank -= below;
+            }
+            const uint32_t median = prefix, need_eq = rank;
+            uint32_t run_l = 0, run_e = 0;
+            for (int i0 = 0; i0 < cnt; i0 += kWave) {
+                const int i = i0 + lane;
+                const bool valid = i < cnt;
+                uint32_t v = 0;
+                if (valid)
+                    v = s_x[a][base + i] - lo;
+                const bool less = valid && v < median;
+                const bool eq = valid && v == median;
+                const uint64_t ml = __ballot(less), me = __ballot(eq);
+                const uint32_t lbefore = run_l + (uint32_t)__popcll(ml & lanes_below());
+                const uint32_t ebefore = run_e + (uint32_t)__popcll(me & lanes_below());
+                run_l += (uint32_t)__popcll(ml);
+                run_e += (uint32_t)__popcll(me);
+                if (valid) {
+                    const bool left = less || (eq && ebefore < need_eq);
+                    const uint32_t left_before = lbefore + (ebefore < need_eq ? ebefore : need_eq);
+                    const uint32_t dst = left ? left_before : (uint32_t)half + ((uint32_t)i - left_before);
+                    s_dst[base + i] = (uint16_t)(base + dst);
+                }
             }
         }
-        // apply the permutation
+        __syncthreads();
+        // apply the permutation through registers
         uint32_t tx[PER][D], tid[PER];
+        uint32_t td[PER];
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
             const int i = r * kThreads + threadIdx.x;
             if (i < cnt0) {
-                const int src = s_slot[i];
 #pragma unroll
                 for (int k = 0; k < D; ++k)
-                    tx[r][k] = s_x[k][src];
-                tid[r] = s_id[src];
+                    tx[r][k] = s_x[k][i];
+                tid[r] = s_id[i];
+                td[r] = s_dst[i];
             }
         }
         __syncthreads();
@@ -591,8 +696,8 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
             if (i < cnt0) {
 #pragma unroll
                 for (int k = 0; k < D; ++k)
-                    s_x[k][i] = tx[r][k];
-                s_id[i] = tid[r];
+                    s_x[k][td[r]] = tx[r][k];
+                s_id[td[r]] = tid[r];
             }
         }
         __syncthreads();
@@ -604,6 +709,25 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
             coords[(s0 + i) * D + k] = (C)((int64_t)origin.v[k] + (int64_t)s_x[k][i]);
         sidx[s0 + i] = (int32_t)s_id[i];
     }
+}
+
+// Digit width of a top level: 11 bits while the level has at most 256 nodes
+// (fewer passes), 8 bits below (small histograms for many nodes).
+constexpr int kWideLevels = 8;
+
+inline int level_bits(int j) { return j <= kWideLevels ? 11 : 8; }
+
+template <typename C, int D, int BITS>
+void launch_level(const uint32_t *Xin, const uint32_t *Iin, uint32_t *Xout, uint32_t *Iout, int64_t n, int j, int h,
+                  int passes, const uint32_t *bj, uint32_t *bj1, uint32_t *hj, NodeSplit *split, uint32_t *cnt_less,
+                  uint32_t *cnt_eq, C *box, Origin origin, unsigned grid, unsigned tiles, hipStream_t s) {
+    for (int p = 0; p < passes; ++p)
+        hipLaunchKernelGGL((k_sel_hist<D, BITS>), dim3(grid), dim3(kThreads), 0, s, Xin, n, j, h, bj, hj, p);
+    hipLaunchKernelGGL((k_part_count<C, D, BITS>), dim3(grid), dim3(kThreads), 0, s, Xin, n, j, h, bj, bj1, hj, split,
+                       cnt_less, cnt_eq, box, origin);
+    hipLaunchKernelGGL(k_part_scan, dim3(2), dim3(kThreads), 0, s, cnt_less, cnt_eq, (int)tiles);
+    hipLaunchKernelGGL((k_part_scatter<D>), dim3(grid), dim3(kThreads), 0, s, Xin, Iin, Xout, Iout, n, j, h, split,
+                       cnt_less, cnt_eq, bj1);
 }
 
 template <typename C, int D>
@@ -637,32 +761,39 @@ dpc_status build_kd(const int32_t *points, Workspace &ws, Index &ix) {
         DPC_TRY(ws.alloc(&XB, (size_t)D * n));
         DPC_TRY(ws.alloc(&IB, n));
         const int64_t tiles = (n + kTile - 1) / kTile;
-        // node boxes of levels 0..jb (heap order, relative coordinates)
+        const int wbits = widest ? 32 - __builtin_clz(widest) : 0;
+        // histogram words of every top level: passes x nodes x bins
+        int64_t hist_off[64];
+        int64_t hist_words = 0;
+        for (int j = 0; j < jb; ++j) {
+            const int bits = level_bits(j);
+            hist_off[j] = hist_words;
+            hist_words += (int64_t)((wbits + bits - 1) / bits) * (1ll << j) * (1ll << bits);
+        }
         uint32_t *nboxes, *hist, *cnt_less, *cnt_eq;
         NodeSplit *split;
         DPC_TRY(ws.alloc(&nboxes, (size_t)(2ll << jb) * 2 * D));
-        const int64_t hist_words = (int64_t)kMaxPasses * kBins * ((1ll << jb) - 1);
-        DPC_TRY(ws.alloc(&hist, (size_t)hist_words));
+        DPC_TRY(ws.alloc(&hist, (size_t)(hist_words > 0 ? hist_words : 1)));
         DPC_TRY(ws.alloc(&split, (size_t)1 << (jb - 1)));
         DPC_TRY(ws.alloc(&cnt_less, (size_t)tiles));
         DPC_TRY(ws.alloc(&cnt_eq, (size_t)tiles));
-        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(hist_words, kThreads)), dim3(kThreads), 0, s, hist, hist_words,
-                           0u);
+        if (hist_words > 0)
+            hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(hist_words, kThreads)), dim3(kThreads), 0, s, hist,
+                               hist_words, 0u);
         hipLaunchKernelGGL((k_root_box<D>), dim3(1), dim3(kWave), 0, s, nboxes + 2 * D, spans);
-        const int passes = (int)((widest ? 32 - __builtin_clz(widest) : 0) + kDigits - 1) / kDigits;
         const unsigned grid = (unsigned)tiles;
         uint32_t *Xin = XA, *Xout = XB, *Iin = IA, *Iout = IB;
         for (int j = 0; j < jb; ++j) {
             const uint32_t *bj = nboxes + (1ll << j) * 2 * D;  // level j boxes start at heap index 2^j
             uint32_t *bj1 = nboxes + (2ll << j) * 2 * D;
-            uint32_t *hj = hist + (int64_t)kMaxPasses * kBins * ((1ll << j) - 1);
-            for (int p = 0; p < passes; ++p)
-                hipLaunchKernelGGL((k_sel_hist<D>), dim3(grid), dim3(kThreads), 0, s, Xin, n, j, h, bj, hj, p);
-            hipLaunchKernelGGL((k_part_count<C, D>), dim3(grid), dim3(kThreads), 0, s, Xin, n, j, h, bj, bj1, hj, split,
-                               cnt_less, cnt_eq, box, origin);
-            hipLaunchKernelGGL(k_part_scan, dim3(2), dim3(kThreads), 0, s, cnt_less, cnt_eq, (int)tiles);
-            hipLaunchKernelGGL((k_part_scatter<D>), dim3(grid), dim3(kThreads), 0, s, Xin, Iin, Xout, Iout, n, j, h,
-                               split, cnt_less, cnt_eq, bj1);
+            const int bits = level_bits(j);
+            const int passes = (wbits + bits - 1) / bits;
+            if (bits == 11)
+                launch_level<C, D, 11>(Xin, Iin, Xout, Iout, n, j, h, passes, bj, bj1, hist + hist_off[j], split,
+                                       cnt_less, cnt_eq, box, origin, grid, (unsigned)tiles, s);
+            else
+                launch_level<C, D, 8>(Xin, Iin, Xout, Iout, n, j, h, passes, bj, bj1, hist + hist_off[j], split,
+                                      cnt_less, cnt_eq, box, origin, grid, (unsigned)tiles, s);
             DPC_HIP(hipGetLastError());
             uint32_t *t = Xin;
             Xin = Xout;

@@ -123,7 +123,7 @@ def test_random_tiny_against_oracle():
         assert_same(got, want, f"case {case} n={n} d={d} span={span} d_cut={d_cut}")
 
 
-RAGGED = [1, 2, 31, 32, 33, 63, 64, 65, 127, 129, 255, 257, 1000, 2047, 4095, 4096, 4097, 8193]
+RAGGED = [1, 2, 31, 32, 33, 34, 39, 63, 64, 65, 97, 127, 129, 255, 257, 1000, 2047, 2049, 4095, 4096, 4097, 8193]
 
 
 @pytest.mark.parametrize("n", RAGGED)

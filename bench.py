@@ -1,10 +1,16 @@
 """Throughput of exact Density Peaks Clustering on one MI355X.
 
-One step = one dpc_run over the whole point set: bounds, Morton sort, index
-build, density, priority keys, dependent points and labels (every step of
-the method), with the points already resident in HBM.  Prints one JSON line.
+One step = one dpc_run over the whole point set: coordinate bounds, k-d tree
+build, density, priority keys, dependent points and labels (every step of the
+method), with the points already resident in HBM.  The workload is the
+10-million-point 2-D variable-density set (varden2d_10m, see datagen).
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME]
+Prints one JSON line: throughput, the roofline of the dominant kernel (its
+average GPU time measured with HIP events on the launch stream during the
+timed steps; its algorithmic work from one extra instrumented run outside the
+timed region) and the plain O(n^2) CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -17,17 +23,74 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "points/sec end-to-end exact DPC (10M 2D, 1 GPU); batched instances/s; p99 ms"
+# MI355X published peaks
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # 256 CUs x 64 lanes x 2.4 GHz x 2 (an FMA counts twice)
+PEAK_HBM_GBPS = 8000.0
+ORACLE_SAMPLE = 32768            # points of the CPU-baseline sample
+
+
+def arith_of(points) -> str:
+    """Which exact arithmetic the library uses for these points (its rule)."""
+    import numpy as np
+
+    span = points.max(axis=0).astype(np.int64) - points.min(axis=0).astype(np.int64)
+    s = sum(int(w) * int(w) for w in span)
+    return "f64" if s < (1 << 53) else "int64"
+
+
+def profiled_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None if there is none for this workload or the kernel's
+    sources changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"traversal_{workload}_hbm_bytes.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        prof = json.load(f)
+    k = prof.get("kernels", {}).get(kernel)
+    if k is None:
+        return None
+    h = hashlib.sha256()
+    for src in k["sources"]:
+        with open(os.path.join(ROOT, "paper_2305_11335_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    return k["bytes"] if h.hexdigest() == k["source_sha256"] else None
+
+
+def cpu_baseline(inst) -> dict:
+    """The oracle (single-threaded C, O(n^2)) on the first ORACLE_SAMPLE points."""
+    import numpy as np
+
+    import oracle
+
+    m = min(ORACLE_SAMPLE, inst.n)
+    pts = np.ascontiguousarray(inst.points[:m])
+    d_cut = inst.d_cut * (inst.n / m) ** (1.0 / inst.d)  # same expected density as the full set
+    oracle.run(pts[:256], d_cut, inst.rho_min, inst.delta_min)  # load the library
+    t0 = time.perf_counter()
+    oracle.run(pts, d_cut, inst.rho_min, inst.delta_min)
+    dt = time.perf_counter() - t0
+    return {"value": m / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {m} points of {inst.name} (input order is a seeded shuffle), d_cut scaled by "
+                      f"(n/m)^(1/d) to {d_cut:.3f} for the same expected density; whole method, one thread, "
+                      f"{dt:.2f} s"}
+
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="varden2d_10m")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this build runs on one GPU only: the hot path is single-GPU (see DESIGN.md for how it "
-              "would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path; run with --gpus 1", file=sys.stderr)
         return 2
 
     import torch
@@ -37,21 +100,54 @@ def main() -> int:
 
     inst = datagen.make(args.workload)
     dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
     P = torch.from_numpy(inst.points).to(dev)
-    n = inst.n
+    n, d = inst.n, inst.d
     out = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
            torch.empty(n, dtype=torch.int64, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+    stream = torch.cuda.current_stream()
+
+    def step(**kw):
+        dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, out=out, stream=stream, **kw)
+
     for _ in range(args.warmup):
-        dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, out=out)
+        step()
     torch.cuda.synchronize()
+    stage_ms = {k: 0.0 for k in dpc.STAGES}
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, out=out)
+        step(time_stages=True)
+        for k, v in dpc.last_stats()["stage_ms"].items():
+            stage_ms[k] += v
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1000.0 / max(args.steps, 1)
+    stage_ms = {k: v / max(args.steps, 1) for k, v in stage_ms.items()}
+
+    # work of the two traversal kernels, from one instrumented run (not timed)
+    step(count_work=True)
+    work = dpc.last_stats()
+    torch.cuda.synchronize()
+
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    # dominant kernel: the longer of the two traversals (each stage is one kernel)
+    dom = max(("density", "dependent"), key=lambda k: stage_ms[k])
+    pairs = work["density_pairs"] if dom == "density" else work["dependent_pairs"]
+    flops_per_pair = 3 * d - 1  # d subtractions, d squares, d - 1 additions of one exact squared distance
+    kernel_s = stage_ms[dom] / 1000.0
+    achieved = pairs * flops_per_pair / kernel_s / 1e12
+    roofline = {"bound": "alu", "kernel": f"k_{dom}", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+                "traffic": profiled_traffic(inst.name, f"k_{dom}"),
+                "kernel_ms": stage_ms[dom], "pair_tests_per_launch": pairs, "flops_per_pair_test": flops_per_pair}
+
     rec = {
-        "metric": "points/sec end-to-end exact DPC (10M 2D, 1 GPU)",
+        "metric": METRIC,
         "value": n / (ms / 1000.0),
         "unit": "points/s",
         "n_gpus": 1,
@@ -61,11 +157,17 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32 coords, exact f64/int64 squared distances",
-        "data": "synthetic",
-        "config": {"workload": inst.name, "n": n, "d": inst.d, "d_cut": inst.d_cut, "rho_min": inst.rho_min,
+        "dtype": arith_of(inst.points),
+        "data": "synthetic (seeded generator, see datagen)",
+        "config": {"workload": inst.name, "n": n, "d": d, "d_cut": inst.d_cut, "rho_min": inst.rho_min,
                    "delta_min": inst.delta_min, "seed": inst.seed},
+        "stage_ms": stage_ms,
+        "work": {k: work[k] for k in ("density_pairs", "density_nodes", "density_contained", "dependent_pairs",
+                                      "dependent_nodes")},
+        "roofline": roofline,
     }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(rec), flush=True)
     return 0
 

@@ -82,6 +82,34 @@ typedef enum {
  * Section 4.3, Algorithm 1 does; the others get (-1, INT64_MAX).  Labels do
  * not change. */
 #define DPC_SKIP_NOISE_DEPENDENTS 1u
+/* dpc_run flag: record HIP events on the call's stream around each step, for
+ * dpc_last_stats.  Adds no synchronisation to the call. */
+#define DPC_TIME_STAGES 2u
+/* dpc_run flag: run instrumented kernels that count the work they do (slower;
+ * for measurement only).  The counts are read back before the call returns. */
+#define DPC_COUNT_WORK 4u
+
+/* Steps of dpc_run timed by DPC_TIME_STAGES. */
+enum {
+    DPC_STAGE_INDEX = 0,     /* bounds (with the host read-back) and k-d tree build */
+    DPC_STAGE_DENSITY = 1,   /* density kernel */
+    DPC_STAGE_PRIORITY = 2,  /* priority keys and per-node maximum keys */
+    DPC_STAGE_DEPENDENT = 3, /* dependent-point kernel */
+    DPC_STAGE_LABELS = 4,    /* cluster labels */
+    DPC_STAGES = 5
+};
+
+/* Measurements of the most recent dpc_run on the calling host thread that
+ * passed DPC_TIME_STAGES and/or DPC_COUNT_WORK. */
+typedef struct {
+    uint32_t flags;                /* which of the two were recorded */
+    double stage_ms[DPC_STAGES];   /* GPU time per step, from the events */
+    int64_t density_pairs;         /* point-pair distance tests, density step */
+    int64_t density_nodes;         /* node-box tests by query lanes, density step */
+    int64_t density_contained;     /* points counted through whole contained nodes (Section 6.1) */
+    int64_t dependent_pairs;       /* point-pair tests of higher-priority candidates, dependent step */
+    int64_t dependent_nodes;       /* node-box tests by query lanes, dependent step */
+} dpc_stats;
 
 /*
  * Density (Section 3, Definition 1; Section 6.1 for the counting of whole
@@ -124,12 +152,21 @@ DPC_API int dpc_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const
 
 /*
  * The whole method: density, dependent points and labels, sharing one
- * spatial index (the three steps of Section 1).  flags: 0 or
- * DPC_SKIP_NOISE_DEPENDENTS.  Output arrays as above; all four are written.
+ * spatial index (the three steps of Section 1).  flags: any combination of
+ * DPC_SKIP_NOISE_DEPENDENTS, DPC_TIME_STAGES and DPC_COUNT_WORK.  Output
+ * arrays as above; all four are written.
  */
 DPC_API int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,
             double delta_min, uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2,
             int32_t *label, hipStream_t stream);
+
+/*
+ * Diagnostics: copies the measurements of the calling thread's most recent
+ * dpc_run made with DPC_TIME_STAGES or DPC_COUNT_WORK into *out, waiting for
+ * that call's recorded events first.  DPC_ERR_INVALID_ARG if out is NULL or
+ * no such call was made on this thread.  Not part of the method.
+ */
+DPC_API int dpc_last_stats(dpc_stats *out);
 
 /* Static description of a status code; never NULL. */
 DPC_API const char *dpc_status_str(int status);

@@ -11,9 +11,11 @@ from ._binding import (  # noqa: F401
     INF,
     LIB_PATH,
     SKIP_NOISE_DEPENDENTS,
+    STAGES,
     cluster,
     density,
     dependent,
+    last_stats,
     load,
     run,
     square_threshold,

@@ -15,10 +15,20 @@ LIB_PATH = os.path.join(HERE, "libdpc.so")
 
 OK, ERR_INVALID_ARG, ERR_RANGE, ERR_NOT_FOREST, ERR_OOM, ERR_HIP = range(6)
 SKIP_NOISE_DEPENDENTS = 1
+TIME_STAGES = 2
+COUNT_WORK = 4
 INF = (1 << 63) - 1
+STAGES = ("index", "density", "priority", "dependent", "labels")
 
-EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_status_str",
+EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_last_stats", "dpc_status_str",
             "dpc_square_threshold")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("stage_ms", ctypes.c_double * len(STAGES)),
+                ("density_pairs", ctypes.c_int64), ("density_nodes", ctypes.c_int64),
+                ("density_contained", ctypes.c_int64), ("dependent_pairs", ctypes.c_int64),
+                ("dependent_nodes", ctypes.c_int64)]
 
 _lib = None
 
@@ -50,6 +60,8 @@ def load():
     lib.dpc_status_str.restype = ctypes.c_char_p
     lib.dpc_square_threshold.argtypes = [dbl, i32, P]
     lib.dpc_square_threshold.restype = ctypes.c_int
+    lib.dpc_last_stats.argtypes = [ctypes.POINTER(Stats)]
+    lib.dpc_last_stats.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -153,9 +165,24 @@ def cluster(rho, dep, delta2, rho_min: int, delta_min: float, label=None, stream
     return label
 
 
+def last_stats() -> dict:
+    """Measurements of this thread's last run() made with time_stages/count_work."""
+    s = Stats()
+    st = load().dpc_last_stats(ctypes.byref(s))
+    if st != OK:
+        raise DPCError(st, "dpc_last_stats")
+    return {"flags": s.flags, "stage_ms": dict(zip(STAGES, list(s.stage_ms))),
+            "density_pairs": s.density_pairs, "density_nodes": s.density_nodes,
+            "density_contained": s.density_contained, "dependent_pairs": s.dependent_pairs,
+            "dependent_nodes": s.dependent_nodes}
+
+
 def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool = False, out=None,
-        stream=None):
-    """(rho, dep, delta2, label) of the whole method on device points."""
+        stream=None, time_stages: bool = False, count_work: bool = False):
+    """(rho, dep, delta2, label) of the whole method on device points.
+
+    time_stages / count_work record per-step GPU times / work counters of
+    this call for last_stats() (measurement only)."""
     torch = _torch()
     n, d = _check_points(points)
     dev = points.device
@@ -165,7 +192,8 @@ def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool =
     dep = _out(out[1], n, torch.int32, dev)
     delta2 = _out(out[2], n, torch.int64, dev)
     label = _out(out[3], n, torch.int32, dev)
-    flags = SKIP_NOISE_DEPENDENTS if skip_noise else 0
+    flags = (SKIP_NOISE_DEPENDENTS if skip_noise else 0) | (TIME_STAGES if time_stages else 0) \
+        | (COUNT_WORK if count_work else 0)
     st = load().dpc_run(_ptr(points), n, d, float(d_cut), int(rho_min), float(delta_min), flags, _ptr(rho),
                         _ptr(dep), _ptr(delta2), _ptr(label), _stream(stream))
     if st != OK:

@@ -88,6 +88,94 @@ hipMemPool_t workspace_pool() {
 
 namespace {
 
+__global__ void k_zero_counters(int64_t *c) {
+    if (threadIdx.x < kCounters)
+        c[threadIdx.x] = 0;
+}
+
+// Measurements of dpc_run calls made with DPC_TIME_STAGES / DPC_COUNT_WORK,
+// kept per host thread.  Events are created once per thread and device.
+struct ThreadStats {
+    bool valid = false;
+    uint32_t flags = 0;
+    int device = -1;
+    hipEvent_t ev[DPC_STAGES + 1] = {};
+    int64_t counters[kCounters] = {};
+};
+
+thread_local ThreadStats t_stats;
+
+class RunRecorder {
+  public:
+    RunRecorder(uint32_t flags, hipStream_t s)
+        : flags_(flags & (DPC_TIME_STAGES | DPC_COUNT_WORK)), stream_(s) {}
+
+    dpc_status begin() {
+        if (flags_ == 0)
+            return DPC_OK;
+        t_stats.valid = false;
+        if (flags_ & DPC_TIME_STAGES) {
+            int dev = 0;
+            DPC_HIP(hipGetDevice(&dev));
+            if (t_stats.device != dev) {
+                for (auto &e : t_stats.ev) {
+                    if (e)
+                        (void)hipEventDestroy(e);
+                    e = nullptr;
+                }
+                for (auto &e : t_stats.ev)
+                    DPC_HIP(hipEventCreate(&e));
+                t_stats.device = dev;
+            }
+            DPC_HIP(hipEventRecord(t_stats.ev[0], stream_));
+        }
+        return DPC_OK;
+    }
+    dpc_status mark(int stage) {
+        if (flags_ & DPC_TIME_STAGES)
+            DPC_HIP(hipEventRecord(t_stats.ev[stage + 1], stream_));
+        return DPC_OK;
+    }
+    dpc_status read_counters(const int64_t *dev) {
+        DPC_HIP(hipMemcpyAsync(t_stats.counters, dev, sizeof(t_stats.counters), hipMemcpyDeviceToHost, stream_));
+        DPC_HIP(hipStreamSynchronize(stream_));
+        return DPC_OK;
+    }
+    void commit() {
+        if (flags_ == 0)
+            return;
+        if (!(flags_ & DPC_COUNT_WORK))
+            for (auto &c : t_stats.counters)
+                c = 0;
+        t_stats.flags = flags_;
+        t_stats.valid = true;
+    }
+    static int last(dpc_stats *out) {
+        if (!t_stats.valid)
+            return DPC_ERR_INVALID_ARG;
+        *out = dpc_stats{};
+        out->flags = t_stats.flags;
+        if (t_stats.flags & DPC_TIME_STAGES) {
+            DPC_HIP(hipEventSynchronize(t_stats.ev[DPC_STAGES]));
+            for (int s = 0; s < DPC_STAGES; ++s) {
+                float ms = 0.0f;
+                DPC_HIP(hipEventElapsedTime(&ms, t_stats.ev[s], t_stats.ev[s + 1]));
+                out->stage_ms[s] = ms;
+            }
+        }
+        out->density_pairs = t_stats.counters[kDensityPairs];
+        out->density_nodes = t_stats.counters[kDensityNodes];
+        out->density_contained = t_stats.counters[kDensityContained];
+        out->dependent_pairs = t_stats.counters[kDependentPairs];
+        out->dependent_nodes = t_stats.counters[kDependentNodes];
+        return DPC_OK;
+    }
+
+  private:
+    uint32_t flags_;
+    hipStream_t stream_;
+};
+
 bool bad_shape(int64_t n, int32_t d) {
     return n < 0 || n > (int64_t)std::numeric_limits<int32_t>::max() - 1 || d < 1 || d > kMaxDim;
 }
@@ -139,7 +227,7 @@ int dpc_density(const int32_t *points, int64_t n, int32_t d, double d_cut, int32
     DPC_TRY(build_index(points, n, d, T, ws, ix));
     int32_t *srho;
     DPC_TRY(ws.alloc(&srho, n));
-    return launch_density(ix, T, srho, rho, stream);
+    return launch_density(ix, T, srho, rho, nullptr, stream);
 }
 
 int dpc_dependent(const int32_t *points, int64_t n, int32_t d, const int32_t *rho, int32_t rho_min, int32_t *dep,
@@ -155,7 +243,7 @@ int dpc_dependent(const int32_t *points, int64_t n, int32_t d, const int32_t *rh
     DPC_TRY(build_index(points, n, d, 0, ws, ix));
     DPC_TRY(build_priority(nullptr, rho, ws, ix));
     const int32_t skip_below = rho_min > 0 ? rho_min : std::numeric_limits<int32_t>::min();
-    return launch_dependent(ix, nullptr, skip_below, dep, delta2, stream);
+    return launch_dependent(ix, skip_below, dep, delta2, nullptr, stream);
 }
 
 int dpc_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2, int32_t rho_min,
@@ -175,7 +263,8 @@ int dpc_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t
 
 int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
             uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2, int32_t *label, hipStream_t stream) {
-    if (bad_shape(n, d) || std::isnan(d_cut) || d_cut < 0.0 || rho_min < 0 || (flags & ~DPC_SKIP_NOISE_DEPENDENTS))
+    const uint32_t known = DPC_SKIP_NOISE_DEPENDENTS | DPC_TIME_STAGES | DPC_COUNT_WORK;
+    if (bad_shape(n, d) || std::isnan(d_cut) || d_cut < 0.0 || rho_min < 0 || (flags & ~known))
         return DPC_ERR_INVALID_ARG;
     int64_t T, Td;
     if (delta_threshold(delta_min, &Td) != DPC_OK)
@@ -185,16 +274,39 @@ int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t r
     if (n == 0)
         return DPC_OK;
     DPC_TRY(square_threshold(d_cut, false, &T));
+    RunRecorder rec(flags, stream);
+    DPC_TRY(rec.begin());
     Workspace ws(stream);
+    int64_t *counters = nullptr;
+    if (flags & DPC_COUNT_WORK) {
+        DPC_TRY(ws.alloc(&counters, kCounters));
+        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kWave), 0, stream, counters);
+        DPC_HIP(hipGetLastError());
+    }
     Index ix;
     DPC_TRY(build_index(points, n, d, T, ws, ix));
+    DPC_TRY(rec.mark(DPC_STAGE_INDEX));
     int32_t *srho;
     DPC_TRY(ws.alloc(&srho, n));
-    DPC_TRY(launch_density(ix, T, srho, rho, stream));
+    DPC_TRY(launch_density(ix, T, srho, rho, counters, stream));
+    DPC_TRY(rec.mark(DPC_STAGE_DENSITY));
     DPC_TRY(build_priority(srho, nullptr, ws, ix));
+    DPC_TRY(rec.mark(DPC_STAGE_PRIORITY));
     const int32_t dep_rho_min = (flags & DPC_SKIP_NOISE_DEPENDENTS) ? rho_min : std::numeric_limits<int32_t>::min();
-    DPC_TRY(launch_dependent(ix, srho, dep_rho_min, dep, delta2, stream));
-    return launch_cluster(n, rho, dep, delta2, rho_min, Td, false, label, ws);
+    DPC_TRY(launch_dependent(ix, dep_rho_min, dep, delta2, counters, stream));
+    DPC_TRY(rec.mark(DPC_STAGE_DEPENDENT));
+    DPC_TRY(launch_cluster(n, rho, dep, delta2, rho_min, Td, false, label, ws));
+    DPC_TRY(rec.mark(DPC_STAGE_LABELS));
+    if (counters)
+        DPC_TRY(rec.read_counters(counters));
+    rec.commit();
+    return DPC_OK;
+}
+
+int dpc_last_stats(dpc_stats *out) {
+    if (out == nullptr)
+        return DPC_ERR_INVALID_ARG;
+    return RunRecorder::last(out);
 }
 
 }  // extern "C"

@@ -17,11 +17,36 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Points of one leaf within distance^2 T of x.  The leaf's coordinates are
+// wave-uniform (scalar loads); a batch of kBatch points is loaded before any
+// is used so that the loads overlap.
 template <typename C, int D>
+__device__ inline int32_t count_within(const C (&x)[D], const C *__restrict__ p, int count, C T) {
+    constexpr int kBatch = 8;
+    int32_t c = 0;
+    int t = 0;
+    for (; t + kBatch <= count; t += kBatch) {
+        C q[kBatch][D];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                q[b][k] = p[(t + b) * D + k];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+            c += dist2<C, D>(x, q[b]) <= T ? 1 : 0;
+    }
+    for (; t < count; ++t)
+        c += point_dist2<C, D>(x, p + t * D) <= T ? 1 : 0;
+    return c;
+}
+
+template <typename C, int D, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coords, const C *__restrict__ box,
                                                       int64_t n, int height, C T, int32_t *__restrict__ srho,
-                                                      const int32_t *__restrict__ sidx,
-                                                      int32_t *__restrict__ rho_out) {
+                                                      const int32_t *__restrict__ sidx, int32_t *__restrict__ rho_out,
+                                                      int64_t *counters) {
+    uint64_t n_pairs = 0, n_nodes = 0, n_contained = 0;
     const int lane = __lane_id();
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t q0 = q - lane;
@@ -47,6 +72,8 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
             bool partial = false;
             if (settled >= depth) {
                 settled = INT_MAX;
+                if (STATS)
+                    ++n_nodes;
                 C dmin2, dmax2;
                 box_dist2<C, D>(x, box + (size_t)v * 2 * D, dmin2, dmax2);
                 if (dmin2 > T) {
@@ -54,15 +81,17 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
                 } else if (dmax2 <= T) {
                     cnt += (int32_t)count;
                     settled = depth;
+                    if (STATS)
+                        n_contained += (uint64_t)count;
                 } else {
                     partial = true;
                 }
             }
             if (v >= first_leaf) {
                 if (partial) {
-                    const C *p = coords + start * D;
-                    for (int t = 0; t < (int)count; ++t)
-                        cnt += point_dist2<C, D>(x, p + t * D) <= T ? 1 : 0;
+                    if (STATS)
+                        n_pairs += (uint64_t)count;
+                    cnt += count_within<C, D>(x, coords + start * D, (int)count, T);
                 }
             } else {
                 descend = __ballot(partial) != 0;
@@ -85,18 +114,23 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
         srho[q] = cnt;
         rho_out[sidx[q]] = cnt;
     }
+    if (STATS) {
+        add_wave_count(counters, kDensityPairs, n_pairs);
+        add_wave_count(counters, kDensityNodes, n_nodes);
+        add_wave_count(counters, kDensityContained, n_contained);
+    }
 }
 
-template <typename C>
-dpc_status launch_typed(const Index &ix, C T, int32_t *srho, int32_t *rho_out, hipStream_t s) {
+template <typename C, bool STATS>
+dpc_status launch_typed(const Index &ix, C T, int32_t *srho, int32_t *rho_out, int64_t *counters, hipStream_t s) {
     const C *coords = static_cast<const C *>(ix.coords);
     const C *box = static_cast<const C *>(ix.box);
     const dim3 grid(blocks_for(ix.n, kThreads)), block(kThreads);
     switch (ix.d) {
 #define DPC_DENSITY_CASE(DD)                                                                                    \
     case DD:                                                                                                    \
-        hipLaunchKernelGGL((k_density<C, DD>), grid, block, 0, s, coords, box, ix.n, ix.height, T, srho, ix.sidx, \
-                           rho_out);                                                                            \
+        hipLaunchKernelGGL((k_density<C, DD, STATS>), grid, block, 0, s, coords, box, ix.n, ix.height, T, srho,    \
+                           ix.sidx, rho_out, counters);                                                         \
         break;
         DPC_DENSITY_CASE(1)
         DPC_DENSITY_CASE(2)
@@ -116,13 +150,16 @@ dpc_status launch_typed(const Index &ix, C T, int32_t *srho, int32_t *rho_out, h
 
 }  // namespace
 
-dpc_status launch_density(const Index &ix, int64_t T, int32_t *srho, int32_t *rho_out, hipStream_t s) {
+dpc_status launch_density(const Index &ix, int64_t T, int32_t *srho, int32_t *rho_out, int64_t *counters,
+                          hipStream_t s) {
     if (ix.arith == Arith::F64) {
         // every squared distance is below 2^53, so a larger threshold acts like 2^53
         const double t = T >= (1ll << 53) ? 9007199254740992.0 : (double)T;
-        return launch_typed<double>(ix, t, srho, rho_out, s);
+        return counters ? launch_typed<double, true>(ix, t, srho, rho_out, counters, s)
+                        : launch_typed<double, false>(ix, t, srho, rho_out, nullptr, s);
     }
-    return launch_typed<int64_t>(ix, T, srho, rho_out, s);
+    return counters ? launch_typed<int64_t, true>(ix, T, srho, rho_out, counters, s)
+                    : launch_typed<int64_t, false>(ix, T, srho, rho_out, nullptr, s);
 }
 
 }  // namespace dpc

@@ -18,13 +18,31 @@ namespace {
 
 constexpr int kThreads = 256;
 
-template <typename C, int D>
+// One candidate: keep the lexicographic minimum of (D^2, index) over points
+// of higher priority; a larger low key word means a smaller index.
+template <typename C, int D, bool STATS>
+__device__ inline void consider(const C (&x)[D], const C (&q)[D], uint64_t kj, uint64_t kq, C &best,
+                                uint32_t &best_low, uint64_t &n_pairs) {
+    if (kj > kq) {
+        if (STATS)
+            ++n_pairs;
+        const C s = dist2<C, D>(x, q);
+        const uint32_t low = (uint32_t)kj;
+        if (s < best || (s == best && low > best_low)) {
+            best = s;
+            best_low = low;
+        }
+    }
+}
+
+template <typename C, int D, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ coords, const C *__restrict__ box,
                                                         const uint64_t *__restrict__ skey,
                                                         const uint64_t *__restrict__ maxkey, int64_t n, int height,
                                                         int32_t rho_min, const int32_t *__restrict__ sidx,
                                                         int32_t *__restrict__ dep_out,
-                                                        int64_t *__restrict__ delta2_out) {
+                                                        int64_t *__restrict__ delta2_out, int64_t *counters) {
+    uint64_t n_pairs = 0, n_nodes = 0;
     const int lane = __lane_id();
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t q0 = q - lane;
@@ -52,20 +70,39 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
         uint32_t first_child = 0;
         if (count > 0) {
             bool want = false;
-            if (active && maxkey[v] > kq)
+            if (active && maxkey[v] > kq) {
                 want = box_min_dist2<C, D>(x, box + (size_t)v * 2 * D) <= best;
+                if (STATS)
+                    ++n_nodes;
+            }
             if (v >= first_leaf) {
                 if (want) {
-                    for (int t = 0; t < (int)count; ++t) {
-                        const uint64_t kj = skey[start + t];
-                        if (kj > kq) {
-                            const C s = point_dist2<C, D>(x, coords + (start + t) * D);
-                            const uint32_t low = (uint32_t)kj;
-                            if (s < best || (s == best && low > best_low)) {
-                                best = s;
-                                best_low = low;
-                            }
+                    // keys and coordinates are wave-uniform: load a batch,
+                    // then test it
+                    constexpr int kBatch = 8;
+                    const C *p = coords + start * D;
+                    const uint64_t *kp = skey + start;
+                    int t = 0;
+                    for (; t + kBatch <= (int)count; t += kBatch) {
+                        uint64_t kb[kBatch];
+                        C qb[kBatch][D];
+#pragma unroll
+                        for (int b = 0; b < kBatch; ++b) {
+                            kb[b] = kp[t + b];
+#pragma unroll
+                            for (int k = 0; k < D; ++k)
+                                qb[b][k] = p[(t + b) * D + k];
                         }
+#pragma unroll
+                        for (int b = 0; b < kBatch; ++b)
+                            consider<C, D, STATS>(x, qb[b], kb[b], kq, best, best_low, n_pairs);
+                    }
+                    for (; t < (int)count; ++t) {
+                        C qv[D];
+#pragma unroll
+                        for (int k = 0; k < D; ++k)
+                            qv[k] = p[t * D + k];
+                        consider<C, D, STATS>(x, qv, kp[t], kq, best, best_low, n_pairs);
                     }
                 }
             } else {
@@ -109,18 +146,23 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
             delta2_out[o] = std::numeric_limits<int64_t>::max();
         }
     }
+    if (STATS) {
+        add_wave_count(counters, kDependentPairs, n_pairs);
+        add_wave_count(counters, kDependentNodes, n_nodes);
+    }
 }
 
-template <typename C>
-dpc_status launch_typed(const Index &ix, int32_t rho_min, int32_t *dep, int64_t *delta2, hipStream_t s) {
+template <typename C, bool STATS>
+dpc_status launch_typed(const Index &ix, int32_t rho_min, int32_t *dep, int64_t *delta2, int64_t *counters,
+                        hipStream_t s) {
     const C *coords = static_cast<const C *>(ix.coords);
     const C *box = static_cast<const C *>(ix.box);
     const dim3 grid(blocks_for(ix.n, kThreads)), block(kThreads);
     switch (ix.d) {
 #define DPC_DEP_CASE(DD)                                                                                        \
     case DD:                                                                                                    \
-        hipLaunchKernelGGL((k_dependent<C, DD>), grid, block, 0, s, coords, box, ix.skey, ix.maxkey, ix.n,       \
-                           ix.height, rho_min, ix.sidx, dep, delta2);                                           \
+        hipLaunchKernelGGL((k_dependent<C, DD, STATS>), grid, block, 0, s, coords, box, ix.skey, ix.maxkey, ix.n, \
+                           ix.height, rho_min, ix.sidx, dep, delta2, counters);                                 \
         break;
         DPC_DEP_CASE(1)
         DPC_DEP_CASE(2)
@@ -140,12 +182,13 @@ dpc_status launch_typed(const Index &ix, int32_t rho_min, int32_t *dep, int64_t 
 
 }  // namespace
 
-dpc_status launch_dependent(const Index &ix, const int32_t *srho, int32_t rho_min, int32_t *dep, int64_t *delta2,
+dpc_status launch_dependent(const Index &ix, int32_t rho_min, int32_t *dep, int64_t *delta2, int64_t *counters,
                             hipStream_t s) {
-    (void)srho;
     if (ix.arith == Arith::F64)
-        return launch_typed<double>(ix, rho_min, dep, delta2, s);
-    return launch_typed<int64_t>(ix, rho_min, dep, delta2, s);
+        return counters ? launch_typed<double, true>(ix, rho_min, dep, delta2, counters, s)
+                        : launch_typed<double, false>(ix, rho_min, dep, delta2, nullptr, s);
+    return counters ? launch_typed<int64_t, true>(ix, rho_min, dep, delta2, counters, s)
+                    : launch_typed<int64_t, false>(ix, rho_min, dep, delta2, nullptr, s);
 }
 
 }  // namespace dpc

@@ -96,6 +96,10 @@ struct Workspace {
             return _st;                                    \
     } while (0)
 
+// Work counters of the instrumented kernels (DPC_COUNT_WORK), in the order of
+// the dpc_stats fields.
+enum Counter { kDensityPairs = 0, kDensityNodes, kDensityContained, kDependentPairs, kDependentNodes, kCounters };
+
 // Exact thresholds (host).
 dpc_status square_threshold(double r, bool round_up, int64_t *out);
 
@@ -108,12 +112,13 @@ dpc_status build_priority(const int32_t *rho_sorted_or_null, const int32_t *rho_
 // set); fills ix.coords, ix.sidx and ix.box.
 dpc_status build_kdtree(const int32_t *points, Workspace &ws, Index &ix);
 
-// density.hip
-dpc_status launch_density(const Index &ix, int64_t T, int32_t *srho, int32_t *rho_out, hipStream_t s);
+// density.hip; counters (or nullptr) selects the instrumented kernel
+dpc_status launch_density(const Index &ix, int64_t T, int32_t *srho, int32_t *rho_out, int64_t *counters,
+                          hipStream_t s);
 
-// dependent.hip
-dpc_status launch_dependent(const Index &ix, const int32_t *srho_or_null, int32_t rho_min, int32_t *dep,
-                            int64_t *delta2, hipStream_t s);
+// dependent.hip; points whose density is below rho_min are skipped
+dpc_status launch_dependent(const Index &ix, int32_t rho_min, int32_t *dep, int64_t *delta2, int64_t *counters,
+                            hipStream_t s);
 
 // cluster.hip
 dpc_status launch_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2,

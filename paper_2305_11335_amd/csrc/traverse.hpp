@@ -48,6 +48,17 @@ __device__ inline C box_min_dist2(const C (&x)[D], const C *__restrict__ b) {
 }
 
 template <typename C, int D>
+__device__ inline C dist2(const C (&x)[D], const C (&p)[D]) {
+    C s = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const C t = x[k] - p[k];
+        s += t * t;
+    }
+    return s;
+}
+
+template <typename C, int D>
 __device__ inline C point_dist2(const C (&x)[D], const C *__restrict__ p) {
     C s = 0;
 #pragma unroll
@@ -65,6 +76,18 @@ __device__ inline void node_range(uint32_t v, int depth, int height, int64_t n, 
     const int64_t cap = (int64_t)kLeafSize << sh;
     const int64_t left = n - start;
     count = left < cap ? left : cap;
+}
+
+// Adds a per-lane count into counters[slot] with one atomic per wavefront.
+__device__ inline void add_wave_count(int64_t *counters, int slot, uint64_t v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, o, kWave);
+        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o, kWave);
+        v += ((uint64_t)hi << 32) | lo;
+    }
+    if (__lane_id() == 0)
+        atomicAdd(reinterpret_cast<unsigned long long *>(counters + slot), (unsigned long long)v);
 }
 
 }  // namespace dpc

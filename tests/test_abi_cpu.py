@@ -28,7 +28,7 @@ def _declared():
 
 
 def test_header_declares_the_interface():
-    assert _declared() == sorted(["dpc_cluster", "dpc_density", "dpc_dependent", "dpc_run",
+    assert _declared() == sorted(["dpc_cluster", "dpc_density", "dpc_dependent", "dpc_last_stats", "dpc_run",
                                   "dpc_square_threshold", "dpc_status_str"])
 
 
@@ -110,12 +110,15 @@ def test_argument_errors_before_any_device_work():
     assert _call("dpc_cluster", 5, fake, fake, fake, 0, float("nan"), fake, NULL) == E
     assert _call("dpc_cluster", 5, fake, NULL, fake, 0, 1.0, fake, NULL) == E
     assert _call("dpc_cluster", -2, fake, fake, fake, 0, 1.0, fake, NULL) == E
-    assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 2, fake, fake, fake, fake, NULL) == E
     assert _call("dpc_run", fake, 5, 2, 1.0, -3, 1.0, 0, fake, fake, fake, fake, NULL) == E
     assert _call("dpc_run", fake, 5, 2, 1.0, 0, float("nan"), 0, fake, fake, fake, fake, NULL) == E
     assert _call("dpc_run", fake, 5, 2, float("nan"), 0, 1.0, 0, fake, fake, fake, fake, NULL) == E
     assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 0, fake, fake, NULL, fake, NULL) == E
     assert _call("dpc_run", fake, 5, 0, 1.0, 0, 1.0, 0, fake, fake, fake, fake, NULL) == E
+    assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 8, fake, fake, fake, fake, NULL) == E
+    assert dpc.load().dpc_last_stats(None) == E
+    with pytest.raises(dpc.DPCError):
+        dpc.last_stats()  # no measured call on this thread
 
 
 def test_empty_input_is_a_no_op():

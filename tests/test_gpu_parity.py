@@ -288,3 +288,21 @@ def test_full_size_sampled(name):
     wd, wd2 = oracle.dependent_at(inst.points, rho, q)
     assert np.array_equal(dep[q], wd) and np.array_equal(d2[q], wd2), "sampled dependent"
     check_invariants(inst.points, rho, dep, d2, lab, inst.rho_min, inst.delta_min)
+
+
+def test_measurement_flags_leave_outputs_unchanged():
+    inst = datagen.make("varden2d_1m", n=100_000)
+    say("measurement flags", inst.n)
+    P = dev(inst.points)
+    plain = [t.cpu() for t in dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min)]
+    timed = [t.cpu() for t in dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, time_stages=True)]
+    st = dpc.last_stats()
+    assert all(st["stage_ms"][k] > 0 for k in dpc.STAGES)
+    counted = [t.cpu() for t in dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, count_work=True)]
+    wk = dpc.last_stats()
+    for a, b, c in zip(plain, timed, counted):
+        assert torch.equal(a, b) and torch.equal(a, c)
+    rho = plain[0].numpy().astype(np.int64)
+    # every counted point is either inside a contained node or was tested
+    assert wk["density_contained"] <= int(rho.sum()) <= wk["density_contained"] + wk["density_pairs"]
+    assert wk["dependent_pairs"] >= inst.n - 1 and wk["density_nodes"] > 0 and wk["dependent_nodes"] > 0

@@ -1,21 +1,53 @@
 // Density (Section 3, Definition 1): rho_i = #{ j : D^2(i, j) <= T }.
 //
-// Each wavefront takes 64 consecutive sorted points and walks the tree.  For
-// every node a lane classifies the node's box against its own ball:
+// Each wavefront takes 64 consecutive sorted points (the two leaves below one
+// node, its "home" node) and walks the tree.  For every node a lane classifies
+// the node's box against its own ball:
 //   outside  (nearest corner beyond the radius)   -> nothing to count;
 //   inside   (farthest corner within the radius)  -> add the node's point
 //            count without visiting its points (Section 6.1);
 //   partial  -> the wave descends (a leaf's points are tested one by one).
 // A lane that settled a node skips that node's subtree; it remembers the
 // depth at which it settled, which stays valid while the walk is below it.
+//
+// The walk does not start at the root.  Every point lies in the home node or
+// in the sibling of one of the home node's ancestors; a sibling whose box is
+// more than r = floor(sqrt(T)) away from the home box along some axis holds
+// no point within the radius of any query.  Lane l tests the sibling at depth
+// l, and the walk starts at the parent of the shallowest sibling that may
+// hold such a point (all shallower siblings are known to hold none).
+//
+// Leaf points are compared exactly in one of two ways.  In general the
+// squared distance is formed in the coordinate type.  When the leaf is
+// narrow (widest side at most R - M, where M = r + 1 and d * R^2 < 2^31),
+// the query's offsets from the leaf corner are clamped to [-M, R] and every
+// point's stored 16-bit offsets are subtracted in packed 16-bit lanes and
+// squared and summed by 2-way dot products.  Unclamped offsets give the
+// exact squared distance; a clamped one gives at least M^2 > T, and so does
+// the true distance, since the clamped axis alone differs by at least M.
 #include "traverse.hpp"
 
 #include <climits>
+#include <type_traits>
 
 namespace dpc {
 namespace {
 
 constexpr int kThreads = 256;
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+// Parameters of the packed comparison of narrow leaves.
+struct Narrow {
+    const uint32_t *org;   // leaf corner relative to lo, [n_leaves][D]
+    const uint32_t *ext;   // widest side of each leaf
+    const uint32_t *pack;  // 16-bit offsets from the corner, [n][(D+1)/2]
+    int32_t lo[kMaxDim];   // global minimum per axis
+    int32_t M;             // floor(sqrt(T)) + 1 (at most R + 1)
+    int32_t R;             // largest offset: D * R^2 < 2^31
+    int32_t limit;         // largest widest side of a narrow leaf (R - M; negative: none)
+    int32_t T;             // the threshold (used when limit >= 0, then T < M^2 <= 2^30)
+};
 
 // Points of one leaf within distance^2 T of x.  The leaf's coordinates are
 // wave-uniform (scalar loads); a batch of kBatch points is loaded before any
@@ -41,15 +73,61 @@ __device__ inline int32_t count_within(const C (&x)[D], const C *__restrict__ p,
     return c;
 }
 
+// The same count on a narrow leaf: q holds the query's clamped offsets from
+// the leaf corner, packed like the leaf's points.
+template <int W>
+__device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint32_t *__restrict__ p, int count,
+                                              int32_t T) {
+    constexpr int kBatch = 16 / W > 0 ? 16 / W : 1;
+    short2_t qv[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        qv[w] = __builtin_bit_cast(short2_t, q[w]);
+    int32_t c = 0;
+    int t = 0;
+    for (; t + kBatch <= count; t += kBatch) {
+        uint32_t pb[kBatch][W];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                pb[b][w] = p[(t + b) * W + w];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            int32_t acc = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const short2_t dv = qv[w] - __builtin_bit_cast(short2_t, pb[b][w]);
+                acc = __builtin_amdgcn_sdot2(dv, dv, acc, false);
+            }
+            c += acc <= T ? 1 : 0;
+        }
+    }
+    for (; t < count; ++t) {
+        int32_t acc = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const short2_t dv = qv[w] - __builtin_bit_cast(short2_t, p[t * W + w]);
+            acc = __builtin_amdgcn_sdot2(dv, dv, acc, false);
+        }
+        c += acc <= T ? 1 : 0;
+    }
+    return c;
+}
+
+__device__ inline int32_t clamp_i32(int32_t v, int32_t lo, int32_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
 template <typename C, int D, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coords, const C *__restrict__ box,
-                                                      int64_t n, int height, C T, int32_t *__restrict__ srho,
-                                                      const int32_t *__restrict__ sidx, int32_t *__restrict__ rho_out,
-                                                      int64_t *counters) {
+                                                      int64_t n, int height, C T, C r, Narrow nw,
+                                                      int32_t *__restrict__ srho, const int32_t *__restrict__ sidx,
+                                                      int32_t *__restrict__ rho_out, int64_t *counters) {
+    constexpr bool kPacked = std::is_same<C, double>::value;
+    constexpr int W = (D + 1) / 2;
     uint64_t n_pairs = 0, n_nodes = 0, n_contained = 0;
     const int lane = __lane_id();
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t q0 = q - lane;
+    const int64_t q0 = wave_base(kThreads);
+    const int64_t q = q0 + lane;
     if (q0 >= n)
         return;  // the whole wave lies past the end
     const bool valid = q < n;
@@ -58,12 +136,43 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
 #pragma unroll
     for (int k = 0; k < D; ++k)
         x[k] = coords[qq * D + k];
+    int32_t xi[D] = {};  // offsets from the global minimum (narrow-leaf path)
+    if constexpr (kPacked) {
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            xi[k] = (int32_t)x[k] - nw.lo[k];
+    }
+
+    // home node (depth hd) and the start of the walk
+    const int hd = height > 0 ? height - 1 : 0;
+    const uint32_t home = (1u << hd) + (uint32_t)((q0 / kLeafSize) >> (height - hd));
+    int sd = hd;
+    if (hd > 0) {
+        const C *hb = box + (size_t)home * 2 * D;
+        bool near = false;
+        if (lane >= 1 && lane <= hd) {
+            const uint32_t s = (home >> (hd - lane)) ^ 1u;
+            int64_t st, cnt;
+            node_range(s, lane, height, n, st, cnt);
+            if (cnt > 0) {
+                const C *sb = box + (size_t)s * 2 * D;
+                bool far = false;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    far |= (sb[2 * k] > hb[2 * k + 1] + r) || (sb[2 * k + 1] < hb[2 * k] - r);
+                near = !far;
+            }
+        }
+        const uint64_t m = __ballot(near);
+        if (m)
+            sd = __ffsll((unsigned long long)m) - 2;  // the parent of the first sibling that may count
+    }
 
     int32_t cnt = 0;
     int settled = valid ? INT_MAX : -1;  // depth at which this lane settled the current path
     const uint32_t first_leaf = 1u << height;
-    uint32_t v = 1;
-    int depth = 0;
+    uint32_t v = home >> (hd - sd);
+    int depth = sd;
     for (;;) {
         int64_t start, count;
         node_range(v, depth, height, n, start, count);
@@ -91,7 +200,25 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
                 if (partial) {
                     if (STATS)
                         n_pairs += (uint64_t)count;
-                    cnt += count_within<C, D>(x, coords + start * D, (int)count, T);
+                    const uint32_t c = v - first_leaf;
+                    bool narrow = false;
+                    if constexpr (kPacked)
+                        narrow = (int32_t)nw.ext[c] <= nw.limit;
+                    if (narrow) {
+                        uint32_t qw[W];
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            const int32_t a = clamp_i32(xi[2 * w] - (int32_t)nw.org[(size_t)c * D + 2 * w], -nw.M, nw.R);
+                            const int32_t b = 2 * w + 1 < D ? clamp_i32(xi[2 * w + 1] -
+                                                                            (int32_t)nw.org[(size_t)c * D + 2 * w + 1],
+                                                                        -nw.M, nw.R)
+                                                            : 0;
+                            qw[w] = ((uint32_t)a & 0xFFFFu) | ((uint32_t)b << 16);
+                        }
+                        cnt += count_within_packed<W>(qw, nw.pack + start * W, (int)count, nw.T);
+                    } else {
+                        cnt += count_within<C, D>(x, coords + start * D, (int)count, T);
+                    }
                 }
             } else {
                 descend = __ballot(partial) != 0;
@@ -102,11 +229,12 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
             ++depth;
             continue;
         }
-        while (v & 1u) {
+        // next node of the walk below the start node
+        while (depth > sd && (v & 1u)) {
             v >>= 1;
             --depth;
         }
-        if (v == 0)
+        if (depth == sd)
             break;
         v += 1;
     }
@@ -122,15 +250,16 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
 }
 
 template <typename C, bool STATS>
-dpc_status launch_typed(const Index &ix, C T, int32_t *srho, int32_t *rho_out, int64_t *counters, hipStream_t s) {
+dpc_status launch_typed(const Index &ix, C T, C r, const Narrow &nw, int32_t *srho, int32_t *rho_out,
+                        int64_t *counters, hipStream_t s) {
     const C *coords = static_cast<const C *>(ix.coords);
     const C *box = static_cast<const C *>(ix.box);
     const dim3 grid(blocks_for(ix.n, kThreads)), block(kThreads);
     switch (ix.d) {
 #define DPC_DENSITY_CASE(DD)                                                                                    \
     case DD:                                                                                                    \
-        hipLaunchKernelGGL((k_density<C, DD, STATS>), grid, block, 0, s, coords, box, ix.n, ix.height, T, srho,    \
-                           ix.sidx, rho_out, counters);                                                         \
+        hipLaunchKernelGGL((k_density<C, DD, STATS>), grid, block, 0, s, coords, box, ix.n, ix.height, T, r, nw,   \
+                           srho, ix.sidx, rho_out, counters);                                                   \
         break;
         DPC_DENSITY_CASE(1)
         DPC_DENSITY_CASE(2)
@@ -148,18 +277,42 @@ dpc_status launch_typed(const Index &ix, C T, int32_t *srho, int32_t *rho_out, i
     return DPC_OK;
 }
 
+// floor(sqrt(v)) for v >= 0
+int64_t isqrt(int64_t v) {
+    int64_t r = (int64_t)__builtin_sqrt((double)v);
+    while (r > 0 && (__int128)r * r > v)
+        --r;
+    while ((__int128)(r + 1) * (r + 1) <= v)
+        ++r;
+    return r;
+}
+
 }  // namespace
 
 dpc_status launch_density(const Index &ix, int64_t T, int32_t *srho, int32_t *rho_out, int64_t *counters,
                           hipStream_t s) {
+    const int64_t r = isqrt(T);
+    Narrow nw{};
+    nw.org = ix.leaf_org;
+    nw.ext = ix.leaf_ext;
+    nw.pack = ix.leaf_pack;
+    for (int k = 0; k < kMaxDim; ++k)
+        nw.lo[k] = ix.lo[k];
+    const int64_t R = isqrt((int64_t)INT32_MAX / ix.d) < 32767 ? isqrt((int64_t)INT32_MAX / ix.d) : 32767;
+    const int64_t M = r + 1;
+    nw.R = (int32_t)R;
+    nw.M = (int32_t)(M <= R ? M : R + 1);
+    nw.limit = M <= R ? (int32_t)(R - M) : -1;
+    nw.T = M <= R ? (int32_t)T : 0;
     if (ix.arith == Arith::F64) {
         // every squared distance is below 2^53, so a larger threshold acts like 2^53
         const double t = T >= (1ll << 53) ? 9007199254740992.0 : (double)T;
-        return counters ? launch_typed<double, true>(ix, t, srho, rho_out, counters, s)
-                        : launch_typed<double, false>(ix, t, srho, rho_out, nullptr, s);
+        const double rr = (double)r;
+        return counters ? launch_typed<double, true>(ix, t, rr, nw, srho, rho_out, counters, s)
+                        : launch_typed<double, false>(ix, t, rr, nw, srho, rho_out, nullptr, s);
     }
-    return counters ? launch_typed<int64_t, true>(ix, T, srho, rho_out, counters, s)
-                    : launch_typed<int64_t, false>(ix, T, srho, rho_out, nullptr, s);
+    return counters ? launch_typed<int64_t, true>(ix, T, r, nw, srho, rho_out, counters, s)
+                    : launch_typed<int64_t, false>(ix, T, r, nw, srho, rho_out, nullptr, s);
 }
 
 }  // namespace dpc

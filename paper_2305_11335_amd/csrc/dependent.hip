@@ -7,8 +7,13 @@
 // like any node whose box is farther than the best distance found so far.
 // A node at exactly the best distance is still visited, since it may hold an
 // equally near point of smaller index.  Each wavefront walks the tree with 64
-// consecutive sorted queries; the nearer child (for the first lane that still
-// needs the node) is visited first so the best distances shrink early.
+// consecutive sorted queries, the points of its "home" node (two leaves).
+// The walk goes bottom-up: first the home node, then the sibling subtree of
+// each ancestor of the home node from the deepest up, which together hold
+// every point once; near candidates are met first, so the distance bounds
+// are tight by the time the large subtrees near the root are tested.  Inside
+// a subtree the nearer child (for the first lane that still needs the node)
+// is visited first.
 #include "traverse.hpp"
 
 #include <limits>
@@ -20,19 +25,19 @@ constexpr int kThreads = 256;
 
 // One candidate: keep the lexicographic minimum of (D^2, index) over points
 // of higher priority; a larger low key word means a smaller index.
+// Branch-free: the distance is formed for every candidate and the better
+// pair selected, which is cheaper than diverging per candidate.
 template <typename C, int D, bool STATS>
 __device__ inline void consider(const C (&x)[D], const C (&q)[D], uint64_t kj, uint64_t kq, C &best,
                                 uint32_t &best_low, uint64_t &n_pairs) {
-    if (kj > kq) {
-        if (STATS)
-            ++n_pairs;
-        const C s = dist2<C, D>(x, q);
-        const uint32_t low = (uint32_t)kj;
-        if (s < best || (s == best && low > best_low)) {
-            best = s;
-            best_low = low;
-        }
-    }
+    const bool higher = kj > kq;
+    if (STATS)
+        n_pairs += higher ? 1u : 0u;
+    const C s = dist2<C, D>(x, q);
+    const uint32_t low = (uint32_t)kj;
+    const bool better = higher & ((s < best) | ((s == best) & (low > best_low)));
+    best = better ? s : best;
+    best_low = better ? low : best_low;
 }
 
 template <typename C, int D, bool STATS>
@@ -44,8 +49,8 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                                                         int64_t *__restrict__ delta2_out, int64_t *counters) {
     uint64_t n_pairs = 0, n_nodes = 0;
     const int lane = __lane_id();
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t q0 = q - lane;
+    const int64_t q0 = wave_base(kThreads);
+    const int64_t q = q0 + lane;
     if (q0 >= n)
         return;
     const bool valid = q < n;
@@ -61,8 +66,13 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
     C best = std::numeric_limits<C>::max();
     uint32_t best_low = 0;  // low key word of the best point; 0 = none yet
     const uint32_t first_leaf = 1u << height;
-    uint32_t u = 1, v = 1;  // virtual (visit order) and real node index
-    int depth = 0;
+    // home node; a: the ancestor whose sibling subtree is walked next
+    const int hd = height > 0 ? height - 1 : 0;
+    const uint32_t home = (1u << hd) + (uint32_t)((q0 / kLeafSize) >> (height - hd));
+    uint32_t a = home;
+    int da = hd;
+    uint32_t u = 1, v = home;  // virtual (visit order, relative to the subtree) and real node index
+    int depth = hd;
     for (;;) {
         int64_t start, count;
         node_range(v, depth, height, n, start, count);
@@ -131,10 +141,19 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
             v >>= 1;
             --depth;
         }
-        if (u == 0)
+        if (u != 0) {
+            u += 1;
+            v ^= 1u;
+            continue;
+        }
+        // this subtree is done: the next one is the sibling of the next ancestor
+        if (a <= 1)
             break;
-        u += 1;
-        v ^= 1u;
+        v = a ^ 1u;
+        depth = da;
+        u = 1;
+        a >>= 1;
+        --da;
     }
     if (valid) {
         const int32_t o = sidx[q];

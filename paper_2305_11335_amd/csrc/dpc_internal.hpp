@@ -39,6 +39,13 @@ struct Index {
     void *box = nullptr;        // node boxes [2*n_leaves][d][2] (min, max), like coords
     uint64_t *skey = nullptr;   // priority key of each sorted position [n]
     uint64_t *maxkey = nullptr; // per-node maximum key [2*n_leaves]
+    // Leaf records: the leaf box's lower corner relative to lo [n_leaves][d],
+    // its widest side [n_leaves], and every point's offsets from that corner
+    // as 16-bit halves, two axes per word [n][(d+1)/2] (meaningful only when
+    // the widest side is below 2^16).
+    uint32_t *leaf_org = nullptr;
+    uint32_t *leaf_ext = nullptr;
+    uint32_t *leaf_pack = nullptr;
 };
 
 // The library's stream-ordered memory pool on the current device (created on

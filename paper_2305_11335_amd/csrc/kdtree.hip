@@ -523,7 +523,9 @@ __global__ __launch_bounds__(kThreads) void k_soa_init(const int32_t *__restrict
 template <typename C, int D>
 __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict__ X, const uint32_t *__restrict__ I,
                                                      int64_t n, int jb, int h, Origin origin, C *__restrict__ tree_box,
-                                                     C *__restrict__ coords, int32_t *__restrict__ sidx) {
+                                                     C *__restrict__ coords, int32_t *__restrict__ sidx,
+                                                     uint32_t *__restrict__ leaf_org, uint32_t *__restrict__ leaf_ext,
+                                                     uint32_t *__restrict__ leaf_pack) {
     constexpr int M = Bottom<D>::kSize;
     constexpr int NB = Bottom<D>::kNodes;
     constexpr int PER = M / kThreads;
@@ -582,10 +584,21 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
         __syncthreads();
         for (int u = threadIdx.x; u < nsub; u += kThreads) {
             const int64_t v = (1ll << l) + s0 / S + u;
+            uint32_t ext = 0;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 tree_box[(v * D + k) * 2 + 0] = (C)((int64_t)origin.v[k] + (int64_t)s_box[u][k][0]);
                 tree_box[(v * D + k) * 2 + 1] = (C)((int64_t)origin.v[k] + (int64_t)s_box[u][k][1]);
+                const uint32_t e = s_box[u][k][1] - s_box[u][k][0];
+                ext = e > ext ? e : ext;
+            }
+            if (l == h) {
+                // leaf record: corner (relative to the global minimum) and widest extent
+                const int64_t c = s0 / kLeafSize + u;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    leaf_org[c * D + k] = s_box[u][k][0];
+                leaf_ext[c] = ext;
             }
         }
         if (l == h)
@@ -703,11 +716,21 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
         __syncthreads();
     }
     __syncthreads();
+    constexpr int W = (D + 1) / 2;
     for (int i = threadIdx.x; i < cnt0; i += kThreads) {
 #pragma unroll
         for (int k = 0; k < D; ++k)
             coords[(s0 + i) * D + k] = (C)((int64_t)origin.v[k] + (int64_t)s_x[k][i]);
         sidx[s0 + i] = (int32_t)s_id[i];
+        // offsets from the leaf corner, two 16-bit halves per word (read only
+        // for leaves narrow enough that every offset fits)
+        const int u = i / kLeafSize;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint32_t a = s_x[2 * w][i] - s_box[u][2 * w][0];
+            const uint32_t b = 2 * w + 1 < D ? s_x[2 * w + 1][i] - s_box[u][2 * w + 1][0] : 0u;
+            leaf_pack[(s0 + i) * W + w] = (a & 0xFFFFu) | (b << 16);
+        }
     }
 }
 
@@ -748,6 +771,9 @@ dpc_status build_kd(const int32_t *points, Workspace &ws, Index &ix) {
     DPC_TRY(ws.alloc(&coords, (size_t)n * D));
     DPC_TRY(ws.alloc(&box, (size_t)2 * ix.n_leaves * 2 * D));
     DPC_TRY(ws.alloc(&ix.sidx, n));
+    DPC_TRY(ws.alloc(&ix.leaf_org, (size_t)ix.n_leaves * D));
+    DPC_TRY(ws.alloc(&ix.leaf_ext, (size_t)ix.n_leaves));
+    DPC_TRY(ws.alloc(&ix.leaf_pack, (size_t)n * ((D + 1) / 2)));
     ix.coords = coords;
     ix.box = box;
 
@@ -806,7 +832,7 @@ dpc_status build_kd(const int32_t *points, Workspace &ws, Index &ix) {
         IA = Iin;
     }
     hipLaunchKernelGGL((k_bottom<C, D>), dim3((unsigned)(1ll << jb)), dim3(kThreads), 0, s, XA, IA, n, jb, h, origin,
-                       box, coords, ix.sidx);
+                       box, coords, ix.sidx, ix.leaf_org, ix.leaf_ext, ix.leaf_pack);
     DPC_HIP(hipGetLastError());
     return DPC_OK;
 }

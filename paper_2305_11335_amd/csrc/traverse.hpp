@@ -69,6 +69,13 @@ __device__ inline C point_dist2(const C (&x)[D], const C *__restrict__ p) {
     return s;
 }
 
+// First query position of this wavefront (a value the compiler knows is
+// uniform across the wave, so state derived from it stays scalar).
+__device__ inline int64_t wave_base(int block_threads) {
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    return (int64_t)blockIdx.x * block_threads + (int64_t)w * kWave;
+}
+
 // First sorted position and number of points below node v at `depth`.
 __device__ inline void node_range(uint32_t v, int depth, int height, int64_t n, int64_t &start, int64_t &count) {
     const int sh = height - depth;

@@ -162,8 +162,7 @@ def main() -> int:
         "config": {"workload": inst.name, "n": n, "d": d, "d_cut": inst.d_cut, "rho_min": inst.rho_min,
                    "delta_min": inst.delta_min, "seed": inst.seed},
         "stage_ms": stage_ms,
-        "work": {k: work[k] for k in ("density_pairs", "density_nodes", "density_contained", "dependent_pairs",
-                                      "dependent_nodes")},
+        "work": {k: work[k] for k in dpc.WORK_FIELDS},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

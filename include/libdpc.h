@@ -109,6 +109,11 @@ typedef struct {
     int64_t density_contained;     /* points counted through whole contained nodes (Section 6.1) */
     int64_t dependent_pairs;       /* point-pair tests of higher-priority candidates, dependent step */
     int64_t dependent_nodes;       /* node-box tests by query lanes, dependent step */
+    /* the same walks counted per wavefront (64 queries walk together) */
+    int64_t density_wave_nodes;    /* nodes visited, density step */
+    int64_t density_wave_points;   /* leaf points iterated over (some lane tests them), density step */
+    int64_t dependent_wave_nodes;  /* nodes visited, dependent step */
+    int64_t dependent_wave_points; /* leaf points iterated over, dependent step */
 } dpc_stats;
 
 /*

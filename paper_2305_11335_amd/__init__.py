@@ -12,6 +12,7 @@ from ._binding import (  # noqa: F401
     LIB_PATH,
     SKIP_NOISE_DEPENDENTS,
     STAGES,
+    WORK_FIELDS,
     cluster,
     density,
     dependent,

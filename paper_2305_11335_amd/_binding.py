@@ -28,7 +28,12 @@ class Stats(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("stage_ms", ctypes.c_double * len(STAGES)),
                 ("density_pairs", ctypes.c_int64), ("density_nodes", ctypes.c_int64),
                 ("density_contained", ctypes.c_int64), ("dependent_pairs", ctypes.c_int64),
-                ("dependent_nodes", ctypes.c_int64)]
+                ("dependent_nodes", ctypes.c_int64), ("density_wave_nodes", ctypes.c_int64),
+                ("density_wave_points", ctypes.c_int64), ("dependent_wave_nodes", ctypes.c_int64),
+                ("dependent_wave_points", ctypes.c_int64)]
+
+WORK_FIELDS = ("density_pairs", "density_nodes", "density_contained", "dependent_pairs", "dependent_nodes",
+               "density_wave_nodes", "density_wave_points", "dependent_wave_nodes", "dependent_wave_points")
 
 _lib = None
 
@@ -171,10 +176,9 @@ def last_stats() -> dict:
     st = load().dpc_last_stats(ctypes.byref(s))
     if st != OK:
         raise DPCError(st, "dpc_last_stats")
-    return {"flags": s.flags, "stage_ms": dict(zip(STAGES, list(s.stage_ms))),
-            "density_pairs": s.density_pairs, "density_nodes": s.density_nodes,
-            "density_contained": s.density_contained, "dependent_pairs": s.dependent_pairs,
-            "dependent_nodes": s.dependent_nodes}
+    out = {"flags": s.flags, "stage_ms": dict(zip(STAGES, list(s.stage_ms)))}
+    out.update({k: getattr(s, k) for k in WORK_FIELDS})
+    return out
 
 
 def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool = False, out=None,

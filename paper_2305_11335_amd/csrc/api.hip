@@ -168,6 +168,10 @@ class RunRecorder {
         out->density_contained = t_stats.counters[kDensityContained];
         out->dependent_pairs = t_stats.counters[kDependentPairs];
         out->dependent_nodes = t_stats.counters[kDependentNodes];
+        out->density_wave_nodes = t_stats.counters[kDensityWaveNodes];
+        out->density_wave_points = t_stats.counters[kDensityWavePoints];
+        out->dependent_wave_nodes = t_stats.counters[kDependentWaveNodes];
+        out->dependent_wave_points = t_stats.counters[kDependentWavePoints];
         return DPC_OK;
     }
 

@@ -54,7 +54,7 @@ struct Narrow {
 // is used so that the loads overlap.
 template <typename C, int D>
 __device__ inline int32_t count_within(const C (&x)[D], const C *__restrict__ p, int count, C T) {
-    constexpr int kBatch = 8;
+    constexpr int kBatch = D <= 2 ? 8 : (D <= 4 ? 4 : 2);  // within the scalar registers
     int32_t c = 0;
     int t = 0;
     for (; t + kBatch <= count; t += kBatch) {
@@ -78,7 +78,7 @@ __device__ inline int32_t count_within(const C (&x)[D], const C *__restrict__ p,
 template <int W>
 __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint32_t *__restrict__ p, int count,
                                               int32_t T) {
-    constexpr int kBatch = 16 / W > 0 ? 16 / W : 1;
+    constexpr int kBatch = W == 1 ? 16 : (8 / W > 0 ? 8 / W : 1);  // within the scalar registers
     short2_t qv[W];
 #pragma unroll
     for (int w = 0; w < W; ++w)
@@ -117,14 +117,40 @@ __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint
 
 __device__ inline int32_t clamp_i32(int32_t v, int32_t lo, int32_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Nearest and farthest squared distance from x to a box (both relative to
+// lo), with every per-axis gap clamped to M: a gap of M or more already puts
+// the distance above T, and a clamped sum is then still at least M^2 > T, so
+// both comparisons with T come out as with the exact values.  24-bit
+// products suffice (M <= R < 2^15 and d * R^2 < 2^31).
+template <int D>
+__device__ inline void box_dist2_clamped(const int32_t (&xi)[D], const uint32_t *__restrict__ b, int32_t M,
+                                         int32_t &dmin2, int32_t &dmax2) {
+    int32_t mn = 0, mx = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int32_t a = (int32_t)b[2 * k] - xi[k];      // lo - x
+        const int32_t c = xi[k] - (int32_t)b[2 * k + 1];  // x - hi
+        int32_t near = a > c ? a : c;
+        near = near > 0 ? near : 0;
+        near = near < M ? near : M;
+        int32_t farn = a < c ? a : c;  // minus the far gap
+        farn = farn > -M ? farn : -M;
+        mn += __mul24(near, near);
+        mx += __mul24(farn, farn);
+    }
+    dmin2 = mn;
+    dmax2 = mx;
+}
+
 template <typename C, int D, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coords, const C *__restrict__ box,
-                                                      int64_t n, int height, C T, C r, Narrow nw,
+                                                      const uint32_t *__restrict__ rbox, int64_t n, int height, C T,
+                                                      C r, Narrow nw,
                                                       int32_t *__restrict__ srho, const int32_t *__restrict__ sidx,
                                                       int32_t *__restrict__ rho_out, int64_t *counters) {
     constexpr bool kPacked = std::is_same<C, double>::value;
     constexpr int W = (D + 1) / 2;
-    uint64_t n_pairs = 0, n_nodes = 0, n_contained = 0;
+    uint64_t n_pairs = 0, n_nodes = 0, n_contained = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
     const int64_t q0 = wave_base(kThreads);
     const int64_t q = q0 + lane;
@@ -178,16 +204,28 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
         node_range(v, depth, height, n, start, count);
         bool descend = false;
         if (count > 0) {
+            if (STATS)
+                ++w_nodes;
             bool partial = false;
             if (settled >= depth) {
                 settled = INT_MAX;
                 if (STATS)
                     ++n_nodes;
-                C dmin2, dmax2;
-                box_dist2<C, D>(x, box + (size_t)v * 2 * D, dmin2, dmax2);
-                if (dmin2 > T) {
+                bool outside, inside;
+                if (kPacked && nw.limit >= 0) {
+                    int32_t dmin2, dmax2;
+                    box_dist2_clamped<D>(xi, rbox + (size_t)v * 2 * D, nw.M, dmin2, dmax2);
+                    outside = dmin2 > nw.T;
+                    inside = dmax2 <= nw.T;
+                } else {
+                    C dmin2, dmax2;
+                    box_dist2<C, D>(x, box + (size_t)v * 2 * D, dmin2, dmax2);
+                    outside = dmin2 > T;
+                    inside = dmax2 <= T;
+                }
+                if (outside) {
                     settled = depth;
-                } else if (dmax2 <= T) {
+                } else if (inside) {
                     cnt += (int32_t)count;
                     settled = depth;
                     if (STATS)
@@ -197,6 +235,8 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
                 }
             }
             if (v >= first_leaf) {
+                if (STATS && __ballot(partial) != 0)
+                    w_points += (uint64_t)count;
                 if (partial) {
                     if (STATS)
                         n_pairs += (uint64_t)count;
@@ -246,6 +286,8 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
         add_wave_count(counters, kDensityPairs, n_pairs);
         add_wave_count(counters, kDensityNodes, n_nodes);
         add_wave_count(counters, kDensityContained, n_contained);
+        add_wave_count(counters, kDensityWaveNodes, lane == 0 ? w_nodes : 0);
+        add_wave_count(counters, kDensityWavePoints, lane == 0 ? w_points : 0);
     }
 }
 
@@ -258,8 +300,8 @@ dpc_status launch_typed(const Index &ix, C T, C r, const Narrow &nw, int32_t *sr
     switch (ix.d) {
 #define DPC_DENSITY_CASE(DD)                                                                                    \
     case DD:                                                                                                    \
-        hipLaunchKernelGGL((k_density<C, DD, STATS>), grid, block, 0, s, coords, box, ix.n, ix.height, T, r, nw,   \
-                           srho, ix.sidx, rho_out, counters);                                                   \
+        hipLaunchKernelGGL((k_density<C, DD, STATS>), grid, block, 0, s, coords, box, ix.rbox, ix.n, ix.height, T, \
+                           r, nw, srho, ix.sidx, rho_out, counters);                                            \
         break;
         DPC_DENSITY_CASE(1)
         DPC_DENSITY_CASE(2)

@@ -23,6 +23,10 @@ namespace {
 
 constexpr int kThreads = 256;
 
+struct Lo {
+    int32_t v[kMaxDim];  // global minimum per axis
+};
+
 // One candidate: keep the lexicographic minimum of (D^2, index) over points
 // of higher priority; a larger low key word means a smaller index.
 // Branch-free: the distance is formed for every candidate and the better
@@ -43,11 +47,12 @@ __device__ inline void consider(const C (&x)[D], const C (&q)[D], uint64_t kj, u
 template <typename C, int D, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ coords, const C *__restrict__ box,
                                                         const uint64_t *__restrict__ skey,
-                                                        const uint64_t *__restrict__ maxkey, int64_t n, int height,
-                                                        int32_t rho_min, const int32_t *__restrict__ sidx,
+                                                        const uint64_t *__restrict__ maxkey,
+                                                        const uint64_t *__restrict__ split, Lo lo, int64_t n,
+                                                        int height, int32_t rho_min, const int32_t *__restrict__ sidx,
                                                         int32_t *__restrict__ dep_out,
                                                         int64_t *__restrict__ delta2_out, int64_t *counters) {
-    uint64_t n_pairs = 0, n_nodes = 0;
+    uint64_t n_pairs = 0, n_nodes = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
     const int64_t q0 = wave_base(kThreads);
     const int64_t q = q0 + lane;
@@ -62,6 +67,12 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
     const uint64_t kq = skey[qq];
     const int32_t rho_q = (int32_t)((uint32_t)(kq >> 32) ^ 0x80000000u);
     const bool active = valid && rho_q >= rho_min;
+    // the wave's first query, relative to lo: the reference point that
+    // decides which child of a node is searched first
+    uint32_t ref[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        ref[k] = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((int64_t)x[k] - lo.v[k]));
 
     C best = std::numeric_limits<C>::max();
     uint32_t best_low = 0;  // low key word of the best point; 0 = none yet
@@ -79,17 +90,22 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
         bool descend = false;
         uint32_t first_child = 0;
         if (count > 0) {
-            bool want = false;
-            if (active && maxkey[v] > kq) {
-                want = box_min_dist2<C, D>(x, box + (size_t)v * 2 * D) <= best;
-                if (STATS)
-                    ++n_nodes;
-            }
+            if (STATS)
+                ++w_nodes;
+            // key and box are loaded together and tested without branches
+            const uint64_t mk = maxkey[v];
+            const C bd = box_min_dist2<C, D>(x, box + (size_t)v * 2 * D);
+            const bool higher = active && mk > kq;
+            const bool want = higher && bd <= best;
+            if (STATS)
+                n_nodes += higher ? 1u : 0u;
             if (v >= first_leaf) {
+                if (STATS && __ballot(want) != 0)
+                    w_points += (uint64_t)count;
                 if (want) {
                     // keys and coordinates are wave-uniform: load a batch,
                     // then test it
-                    constexpr int kBatch = 8;
+                    constexpr int kBatch = D <= 2 ? 4 : (D <= 4 ? 2 : 1);  // within the scalar registers
                     const C *p = coords + start * D;
                     const uint64_t *kp = skey + start;
                     int t = 0;
@@ -119,13 +135,16 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                 const uint64_t m = __ballot(want);
                 if (m) {
                     descend = true;
-                    // the left child is never empty; the right one may be
+                    // the left child is never empty; the right one may be.
+                    // The child on the reference point's side goes first.
                     if (count > ((int64_t)kLeafSize << (height - depth - 1))) {
-                        const C *bl = box + (size_t)(2 * v) * 2 * D;
-                        const C dl = box_min_dist2<C, D>(x, bl);
-                        const C dr = box_min_dist2<C, D>(x, bl + 2 * D);
-                        const int leader = __ffsll((unsigned long long)m) - 1;
-                        first_child = (uint32_t)__builtin_amdgcn_readlane(dl <= dr ? 0 : 1, leader);
+                        const uint64_t sp = split[v];
+                        const uint32_t axis = (uint32_t)(sp >> 32);
+                        uint32_t r = ref[0];
+#pragma unroll
+                        for (int k = 1; k < D; ++k)
+                            r = axis == (uint32_t)k ? ref[k] : r;
+                        first_child = r < (uint32_t)sp ? 0u : 1u;
                     }
                 }
             }
@@ -157,17 +176,14 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
     }
     if (valid) {
         const int32_t o = sidx[q];
-        if (best_low != 0) {
-            dep_out[o] = (int32_t)(0xFFFFFFFFu - best_low);
-            delta2_out[o] = (int64_t)best;
-        } else {
-            dep_out[o] = -1;
-            delta2_out[o] = std::numeric_limits<int64_t>::max();
-        }
+        dep_out[o] = best_low != 0 ? (int32_t)(0xFFFFFFFFu - best_low) : -1;
+        delta2_out[o] = best_low != 0 ? (int64_t)best : std::numeric_limits<int64_t>::max();
     }
     if (STATS) {
         add_wave_count(counters, kDependentPairs, n_pairs);
         add_wave_count(counters, kDependentNodes, n_nodes);
+        add_wave_count(counters, kDependentWaveNodes, lane == 0 ? w_nodes : 0);
+        add_wave_count(counters, kDependentWavePoints, lane == 0 ? w_points : 0);
     }
 }
 
@@ -177,11 +193,14 @@ dpc_status launch_typed(const Index &ix, int32_t rho_min, int32_t *dep, int64_t 
     const C *coords = static_cast<const C *>(ix.coords);
     const C *box = static_cast<const C *>(ix.box);
     const dim3 grid(blocks_for(ix.n, kThreads)), block(kThreads);
+    Lo lo{};
+    for (int k = 0; k < kMaxDim; ++k)
+        lo.v[k] = ix.lo[k];
     switch (ix.d) {
 #define DPC_DEP_CASE(DD)                                                                                        \
     case DD:                                                                                                    \
-        hipLaunchKernelGGL((k_dependent<C, DD, STATS>), grid, block, 0, s, coords, box, ix.skey, ix.maxkey, ix.n, \
-                           ix.height, rho_min, ix.sidx, dep, delta2, counters);                                 \
+        hipLaunchKernelGGL((k_dependent<C, DD, STATS>), grid, block, 0, s, coords, box, ix.skey, ix.maxkey,        \
+                           ix.split, lo, ix.n, ix.height, rho_min, ix.sidx, dep, delta2, counters);   \
         break;
         DPC_DEP_CASE(1)
         DPC_DEP_CASE(2)

@@ -37,8 +37,13 @@ struct Index {
     void *coords = nullptr;     // sorted coordinates [n][d], double or int64
     int32_t *sidx = nullptr;    // original index of each sorted position [n]
     void *box = nullptr;        // node boxes [2*n_leaves][d][2] (min, max), like coords
+    uint32_t *rbox = nullptr;   // the same boxes relative to lo, as uint32
     uint64_t *skey = nullptr;   // priority key of each sorted position [n]
     uint64_t *maxkey = nullptr; // per-node maximum key [2*n_leaves]
+    // Split of each internal node v < n_leaves: axis << 32 | median offset
+    // from lo along that axis (points below go left).  Only a hint for the
+    // order in which children are searched.
+    uint64_t *split = nullptr;
     // Leaf records: the leaf box's lower corner relative to lo [n_leaves][d],
     // its widest side [n_leaves], and every point's offsets from that corner
     // as 16-bit halves, two axes per word [n][(d+1)/2] (meaningful only when
@@ -105,7 +110,18 @@ struct Workspace {
 
 // Work counters of the instrumented kernels (DPC_COUNT_WORK), in the order of
 // the dpc_stats fields.
-enum Counter { kDensityPairs = 0, kDensityNodes, kDensityContained, kDependentPairs, kDependentNodes, kCounters };
+enum Counter {
+    kDensityPairs = 0,
+    kDensityNodes,
+    kDensityContained,
+    kDependentPairs,
+    kDependentNodes,
+    kDensityWaveNodes,
+    kDensityWavePoints,
+    kDependentWaveNodes,
+    kDependentWavePoints,
+    kCounters
+};
 
 // Exact thresholds (host).
 dpc_status square_threshold(double r, bool round_up, int64_t *out);

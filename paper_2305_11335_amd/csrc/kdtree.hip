@@ -106,25 +106,23 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
+// The kItems values of one wave's items (positions base + r * 64 + lane),
+// loaded without branches so that all loads are in flight together; items
+// past the end read the last element instead and must be ignored.
+__device__ inline void load_items(const uint32_t *__restrict__ a, int64_t n, int64_t base, uint32_t (&out)[kItems]) {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t e = base + (int64_t)r * kWave + __lane_id();
+        out[r] = a[e < n ? e : n - 1];
+    }
+}
+
 // Orders the LDS accesses of the lanes of one wavefront: everything a lane
 // did before is visible to every lane of the wave after.
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Lanes (among `valid` ones) whose NBITS-bit digit equals this lane's.
-template <int NBITS>
-__device__ inline uint64_t match_digit(uint32_t dg, bool valid) {
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < NBITS; ++b) {
-        const bool bit = (dg >> b) & 1u;
-        const uint64_t bb = __ballot(bit);
-        m &= bit ? bb : ~bb;
-    }
-    return m;
 }
 
 // Longest side of a box given as [D][lo, hi] relative coordinates; the lowest
@@ -175,93 +173,127 @@ __device__ inline NodeSelect node_select(const uint32_t *__restrict__ nbox) {
     return s;
 }
 
-// Replays the digit choices of passes [0, upto) from their histograms: the
-// digits of the median found so far (prefix), how many of the node's points
-// lie below the prefix range (less), and the median's rank among the points
-// matching the prefix (rank).
+// State of a node's radix select after some passes: the digits of the
+// median found so far (prefix), how many of the node's points lie below the
+// prefix range (less), and the median's rank among the points matching the
+// prefix (rank).
 struct SelectState {
     uint32_t prefix, less, rank;
 };
 
+// Chooses the digit of one pass from the node's histogram of that pass (all
+// threads of the block take part).
 template <int BITS>
-__device__ inline SelectState replay(const uint32_t *__restrict__ hist_node, int64_t pass_stride, int upto,
-                                     uint32_t half, uint32_t *s_w, uint32_t *s_pick) {
+__device__ inline void pick_digit(const uint32_t *__restrict__ hp, SelectState &st, uint32_t *s_w,
+                                  uint32_t *s_pick) {
     using Dg = Digit<BITS>;
-    SelectState st{0u, 0u, half};
-    for (int p = 0; p < upto; ++p) {
-        const uint32_t *hp = hist_node + (int64_t)p * pass_stride + threadIdx.x * Dg::kPerThread;
-        uint32_t c[Dg::kPerThread];
-        uint32_t mine = 0;
+    uint32_t c[Dg::kPerThread];
+    uint32_t mine = 0;
 #pragma unroll
-        for (int b = 0; b < Dg::kPerThread; ++b) {
-            c[b] = hp[b];
-            mine += c[b];
-        }
-        uint32_t cum = block_incl_scan(mine, s_w) - mine;
-#pragma unroll
-        for (int b = 0; b < Dg::kPerThread; ++b) {
-            if (cum <= st.rank && st.rank < cum + c[b]) {
-                s_pick[0] = threadIdx.x * Dg::kPerThread + b;
-                s_pick[1] = cum;
-            }
-            cum += c[b];
-        }
-        __syncthreads();
-        const uint32_t dg = s_pick[0], below = s_pick[1];
-        __syncthreads();
-        st.prefix = (st.prefix << BITS) | dg;
-        st.less += below;
-        st.rank -= below;
+    for (int b = 0; b < Dg::kPerThread; ++b) {
+        c[b] = hp[threadIdx.x * Dg::kPerThread + b];
+        mine += c[b];
     }
-    return st;
+    uint32_t cum = block_incl_scan(mine, s_w) - mine;
+#pragma unroll
+    for (int b = 0; b < Dg::kPerThread; ++b) {
+        if (cum <= st.rank && st.rank < cum + c[b]) {
+            s_pick[0] = threadIdx.x * Dg::kPerThread + b;
+            s_pick[1] = cum;
+        }
+        cum += c[b];
+    }
+    __syncthreads();
+    const uint32_t dg = s_pick[0], below = s_pick[1];
+    __syncthreads();
+    st.prefix = (st.prefix << BITS) | dg;
+    st.less += below;
+    st.rank -= below;
 }
 
+// One pass of the radix select of every node of level j: each workgroup
+// histograms the digit of the points of `tiles` consecutive tiles (all in one
+// node) that still match the node's prefix, then adds its histogram to the
+// node's (k_sel_pick then chooses the digit).  Several tiles per workgroup
+// keep the number of global additions to one bin low on the first levels,
+// where every workgroup works on one of very few nodes.
 template <int D, int BITS>
 __global__ __launch_bounds__(kThreads) void k_sel_hist(const uint32_t *__restrict__ X, int64_t n, int j, int h,
                                                        const uint32_t *__restrict__ boxes, uint32_t *__restrict__ hist,
-                                                       int pass) {
+                                                       int pass, const SelectState *__restrict__ state, int tiles) {
     using Dg = Digit<BITS>;
     __shared__ uint32_t s_h[Dg::kBins];
-    __shared__ uint32_t s_w[kWaves];
-    __shared__ uint32_t s_pick[2];
-    const int64_t e0 = (int64_t)blockIdx.x * kTile;
-    if (e0 >= n)
+    const int64_t b0 = (int64_t)blockIdx.x * tiles * kTile;
+    if (b0 >= n)
         return;
     const int64_t S = (int64_t)kLeafSize << (h - j);
-    const int64_t t = e0 / S;
+    const int64_t t = b0 / S;
     const NodeGeom g = node_geom(t, S, n);
     const NodeSelect ns = node_select<D, BITS>(boxes + t * 2 * D);
     if (pass >= ns.passes || g.half == g.count)
         return;  // this node's median is already known (or it has no right half)
     const int64_t pass_stride = (1ll << j) * Dg::kBins;
-    const SelectState st = replay<BITS>(hist + t * Dg::kBins, pass_stride, pass, (uint32_t)g.half, s_w, s_pick);
+    const SelectState st = pass == 0 ? SelectState{0u, 0u, (uint32_t)g.half} : state[t];
     const int shift = (ns.passes - 1 - pass) * BITS;
     for (int b = threadIdx.x; b < Dg::kBins; b += kThreads)
         s_h[b] = 0;
     __syncthreads();
     const uint32_t *x = X + (int64_t)ns.axis * n;
     const int w = threadIdx.x / kWave;
+    for (int tt = 0; tt < tiles; ++tt) {
+        const int64_t e0 = b0 + (int64_t)tt * kTile;
+        if (e0 >= n)
+            break;
+        uint32_t xv[kItems];
+        load_items(x, n, e0 + (int64_t)w * kWaveItems, xv);
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t e = e0 + (int64_t)w * kWaveItems + (int64_t)r * kWave + __lane_id();
-        bool match = false;
-        uint32_t dg = 0;
-        if (e < n) {
-            const uint64_t v = (uint64_t)(x[e] - ns.base);
-            match = (v >> (shift + BITS)) == (uint64_t)st.prefix;
-            dg = (uint32_t)(v >> shift) & (Dg::kBins - 1);
+        for (int r = 0; r < kItems; ++r) {
+            const int64_t e = e0 + (int64_t)w * kWaveItems + (int64_t)r * kWave + __lane_id();
+            const uint64_t v = (uint64_t)(xv[r] - ns.base);
+            const bool match = e < n && (v >> (shift + BITS)) == (uint64_t)st.prefix;
+            const uint32_t dg = (uint32_t)(v >> shift) & (Dg::kBins - 1);
+            // clustered points often share one digit across the wave: one
+            // addition then serves them all
+            const uint64_t mm = __ballot(match);
+            const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)dg);
+            if (__ballot(match && dg != d0) == 0) {
+                if (mm != 0 && __lane_id() == 0)
+                    atomicAdd(&s_h[d0], (uint32_t)__popcll(mm));
+            } else if (match) {
+                atomicAdd(&s_h[dg], 1u);
+            }
         }
-        // one LDS update per distinct digit in the wave
-        const uint64_t peers = match_digit<BITS>(dg, match);
-        if (match && (peers & lanes_below()) == 0)
-            atomicAdd(&s_h[dg], (uint32_t)__popcll(peers));
     }
     __syncthreads();
+    uint32_t *hp = hist + (int64_t)pass * pass_stride + t * Dg::kBins;
     for (int b = threadIdx.x; b < Dg::kBins; b += kThreads) {
         const uint32_t c = s_h[b];
         if (c)
-            atomicAdd(&hist[(int64_t)pass * pass_stride + t * Dg::kBins + b], c);
+            atomicAdd(&hp[b], c);
     }
+}
+
+// Chooses each node's digit of this pass from its finished histogram (one
+// workgroup per node) and stores the node's state for the next pass.
+template <int D, int BITS>
+__global__ __launch_bounds__(kThreads) void k_sel_pick(int64_t n, int j, int h, const uint32_t *__restrict__ boxes,
+                                                       const uint32_t *__restrict__ hist, int pass,
+                                                       SelectState *__restrict__ state) {
+    using Dg = Digit<BITS>;
+    __shared__ uint32_t s_w[kWaves];
+    __shared__ uint32_t s_pick[2];
+    const int64_t t = blockIdx.x;
+    const int64_t S = (int64_t)kLeafSize << (h - j);
+    if (t * S >= n)
+        return;
+    const NodeGeom g = node_geom(t, S, n);
+    const NodeSelect ns = node_select<D, BITS>(boxes + t * 2 * D);
+    if (pass >= ns.passes || g.half == g.count)
+        return;
+    SelectState st = pass == 0 ? SelectState{0u, 0u, (uint32_t)g.half} : state[t];
+    pick_digit<BITS>(hist + (int64_t)pass * (1ll << j) * Dg::kBins + t * Dg::kBins, st, s_w, s_pick);
+    if (threadIdx.x == 0)
+        state[t] = st;
 }
 
 struct NodeSplit {
@@ -275,13 +307,11 @@ struct NodeSplit {
 template <typename C, int D, int BITS>
 __global__ __launch_bounds__(kThreads) void k_part_count(const uint32_t *__restrict__ X, int64_t n, int j, int h,
                                                          const uint32_t *__restrict__ boxes,
-                                                         uint32_t *__restrict__ child_boxes,
-                                                         const uint32_t *__restrict__ hist, NodeSplit *__restrict__ split,
-                                                         uint32_t *__restrict__ cnt_less, uint32_t *__restrict__ cnt_eq,
-                                                         C *__restrict__ tree_box, Origin origin) {
-    using Dg = Digit<BITS>;
-    __shared__ uint32_t s_w[kWaves];
-    __shared__ uint32_t s_pick[2];
+                                                         const SelectState *__restrict__ state,
+                                                         NodeSplit *__restrict__ split, uint32_t *__restrict__ cnt_less,
+                                                         uint32_t *__restrict__ cnt_eq, C *__restrict__ tree_box,
+                                                         uint32_t *__restrict__ rel_box, uint64_t *__restrict__ split_hint,
+                                                         Origin origin) {
     __shared__ uint32_t s_c[2][kWaves];
     const int64_t e0 = (int64_t)blockIdx.x * kTile;
     if (e0 >= n)
@@ -292,9 +322,8 @@ __global__ __launch_bounds__(kThreads) void k_part_count(const uint32_t *__restr
     const uint32_t *nb = boxes + t * 2 * D;
     const NodeSelect ns = node_select<D, BITS>(nb);
     const bool all_left = g.half == g.count;
-    SelectState st{0u, 0u, 0u};
-    if (!all_left)
-        st = replay<BITS>(hist + t * Dg::kBins, (1ll << j) * Dg::kBins, ns.passes, (uint32_t)g.half, s_w, s_pick);
+    const SelectState st =
+        (all_left || ns.passes == 0) ? SelectState{0u, 0u, (uint32_t)g.half} : state[t];
     // with every digit chosen, prefix is the exact median and rank its rank
     // among the points equal to it
     if (e0 == g.start && threadIdx.x == 0) {
@@ -305,32 +334,27 @@ __global__ __launch_bounds__(kThreads) void k_part_count(const uint32_t *__restr
         sp.axis = ns.axis;
         sp.all_left = all_left ? 1 : 0;
         split[t] = sp;
+        split_hint[(1ll << j) + t] = ((uint64_t)(uint32_t)sp.axis << 32) | (uint64_t)(sp.base + sp.median);
         const int64_t v = (1ll << j) + t;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             tree_box[(v * D + k) * 2 + 0] = (C)((int64_t)origin.v[k] + (int64_t)nb[2 * k]);
             tree_box[(v * D + k) * 2 + 1] = (C)((int64_t)origin.v[k] + (int64_t)nb[2 * k + 1]);
+            rel_box[(v * D + k) * 2 + 0] = nb[2 * k];
+            rel_box[(v * D + k) * 2 + 1] = nb[2 * k + 1];
         }
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                child_boxes[((2 * t + c) * D + k) * 2 + 0] = 0xFFFFFFFFu;
-                child_boxes[((2 * t + c) * D + k) * 2 + 1] = 0u;
-            }
     }
     const uint32_t *x = X + (int64_t)ns.axis * n;
     const int w = threadIdx.x / kWave;
+    uint32_t xv[kItems];
+    load_items(x, n, e0 + (int64_t)w * kWaveItems, xv);
     uint32_t nl = 0, ne = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const int64_t e = e0 + (int64_t)w * kWaveItems + (int64_t)r * kWave + __lane_id();
-        bool less = false, eq = false;
-        if (e < n) {
-            const uint32_t v = x[e] - ns.base;
-            less = all_left || v < st.prefix;
-            eq = !all_left && v == st.prefix;
-        }
+        const uint32_t v = xv[r] - ns.base;
+        const bool less = e < n && (all_left || v < st.prefix);
+        const bool eq = e < n && !all_left && v == st.prefix;
         nl += (uint32_t)__popcll(__ballot(less));
         ne += (uint32_t)__popcll(__ballot(eq));
     }
@@ -350,24 +374,26 @@ __global__ __launch_bounds__(kThreads) void k_part_count(const uint32_t *__restr
     }
 }
 
-// Exclusive scans of the per-tile counts (block 0: less, block 1: equal).
-__global__ __launch_bounds__(kThreads) void k_part_scan(uint32_t *__restrict__ cnt_less, uint32_t *__restrict__ cnt_eq,
-                                                        int m) {
-    __shared__ uint32_t s_w[kWaves];
-    __shared__ uint32_t s_total;
+// Exclusive scans of the per-tile counts (block 0: less, block 1: equal):
+// each thread sums a contiguous run of tiles, one block scan, then each
+// thread writes its run's prefixes.
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_part_scan(uint32_t *__restrict__ cnt_less,
+                                                            uint32_t *__restrict__ cnt_eq, int m) {
+    __shared__ uint32_t s_w[kScanThreads / kWave];
     uint32_t *a = blockIdx.x == 0 ? cnt_less : cnt_eq;
-    uint32_t carry = 0;
-    for (int c = 0; c < m; c += kThreads) {
-        const int i = c + threadIdx.x;
-        const uint32_t v = i < m ? a[i] : 0u;
-        const uint32_t incl = block_incl_scan(v, s_w);
-        if (i < m)
-            a[i] = carry + incl - v;
-        if (threadIdx.x == kThreads - 1)
-            s_total = incl;
-        __syncthreads();
-        carry += s_total;
-        __syncthreads();
+    const int per = (m + kScanThreads - 1) / kScanThreads;
+    const int b = threadIdx.x * per;
+    const int e = b + per < m ? b + per : m;
+    uint32_t sum = 0;
+    for (int i = b; i < e; ++i)
+        sum += a[i];
+    uint32_t run = block_incl_scan(sum, s_w) - sum;
+    for (int i = b; i < e; ++i) {
+        const uint32_t v = a[i];
+        a[i] = run;
+        run += v;
     }
 }
 
@@ -379,7 +405,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(const uint32_t *__res
                                                            const NodeSplit *__restrict__ split,
                                                            const uint32_t *__restrict__ scan_less,
                                                            const uint32_t *__restrict__ scan_eq,
-                                                           uint32_t *__restrict__ child_boxes) {
+                                                           uint32_t *__restrict__ tile_box) {
     __shared__ uint32_t s_w[2][kWaves];
     __shared__ uint32_t s_box[2][D][2];
     const int64_t e0 = (int64_t)blockIdx.x * kTile;
@@ -399,19 +425,26 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(const uint32_t *__res
         s_box[c][k][1] = 0u;
     }
     const int w = threadIdx.x / kWave;
-    const uint32_t *xa = Xin + (int64_t)sp.axis * n;
+    const int64_t ew = e0 + (int64_t)w * kWaveItems;
+    // every value this thread moves, loaded up front
+    uint32_t xv[D][kItems], iv[kItems];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        load_items(Xin + (int64_t)k * n, n, ew, xv[k]);
+    load_items(Iin, n, ew, iv);
     uint32_t lb[kItems], eb[kItems];
     uint32_t less_bits = 0, eq_bits = 0;
     uint32_t run_l = 0, run_e = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const int64_t e = e0 + (int64_t)w * kWaveItems + (int64_t)r * kWave + __lane_id();
-        bool less = false, eq = false;
-        if (e < n) {
-            const uint32_t v = xa[e] - sp.base;
-            less = sp.all_left || v < sp.median;
-            eq = !sp.all_left && v == sp.median;
-        }
+        const int64_t e = ew + (int64_t)r * kWave + __lane_id();
+        uint32_t va = xv[0][r];
+#pragma unroll
+        for (int k = 1; k < D; ++k)
+            va = sp.axis == k ? xv[k][r] : va;
+        const uint32_t v = va - sp.base;
+        const bool less = e < n && (sp.all_left || v < sp.median);
+        const bool eq = e < n && !sp.all_left && v == sp.median;
         const uint64_t ml = __ballot(less), me = __ballot(eq);
         lb[r] = run_l + (uint32_t)__popcll(ml & lanes_below());
         eb[r] = run_e + (uint32_t)__popcll(me & lanes_below());
@@ -439,7 +472,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(const uint32_t *__res
     }
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const int64_t e = e0 + (int64_t)w * kWaveItems + (int64_t)r * kWave + __lane_id();
+        const int64_t e = ew + (int64_t)r * kWave + __lane_id();
         if (e >= n)
             continue;
         const bool less = (less_bits >> r) & 1u, eq = (eq_bits >> r) & 1u;
@@ -452,7 +485,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(const uint32_t *__res
         const int64_t dst = left ? g.start + left_before : g.start + g.half + (pos - left_before);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const uint32_t v = Xin[(int64_t)k * n + e];
+            const uint32_t v = xv[k][r];
             Xout[(int64_t)k * n + dst] = v;
             if (left) {
                 lmin[k] = v < lmin[k] ? v : lmin[k];
@@ -462,7 +495,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(const uint32_t *__res
                 rmax[k] = v > rmax[k] ? v : rmax[k];
             }
         }
-        Iout[dst] = Iin[e];
+        Iout[dst] = iv[r];
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -480,12 +513,52 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(const uint32_t *__res
         }
     }
     __syncthreads();
-    if (threadIdx.x < 2 * D) {
-        const int c = threadIdx.x / D, k = threadIdx.x % D;
-        if (s_box[c][k][0] <= s_box[c][k][1]) {
-            atomicMin(&child_boxes[((2 * t + c) * D + k) * 2 + 0], s_box[c][k][0]);
-            atomicMax(&child_boxes[((2 * t + c) * D + k) * 2 + 1], s_box[c][k][1]);
+    // this tile's share of the two children's boxes (an empty share has
+    // min > max); k_box_reduce combines the shares of a node's tiles
+    if (threadIdx.x < 4 * D)
+        tile_box[(int64_t)blockIdx.x * 4 * D + threadIdx.x] = (&s_box[0][0][0])[threadIdx.x];
+}
+
+// The children's boxes of every node of level j from the per-tile shares
+// (one workgroup per node).
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_box_reduce(int64_t n, int j, int h,
+                                                         const uint32_t *__restrict__ tile_box,
+                                                         uint32_t *__restrict__ child_boxes) {
+    __shared__ uint32_t s_r[kWaves][4 * D];
+    const int64_t t = blockIdx.x;
+    const int64_t S = (int64_t)kLeafSize << (h - j);
+    if (t * S >= n)
+        return;
+    const NodeGeom g = node_geom(t, S, n);
+    const int64_t t0 = g.start / kTile, t1 = (g.start + g.count + kTile - 1) / kTile;
+    uint32_t acc[4 * D];
+#pragma unroll
+    for (int i = 0; i < 4 * D; ++i)
+        acc[i] = (i & 1) ? 0u : 0xFFFFFFFFu;  // [c][k][min, max]
+    for (int64_t q = t0 + threadIdx.x; q < t1; q += kThreads) {
+#pragma unroll
+        for (int i = 0; i < 4 * D; ++i) {
+            const uint32_t v = tile_box[q * 4 * D + i];
+            acc[i] = (i & 1) ? (v > acc[i] ? v : acc[i]) : (v < acc[i] ? v : acc[i]);
         }
+    }
+#pragma unroll
+    for (int i = 0; i < 4 * D; ++i)
+        acc[i] = (i & 1) ? wave_max_u32(acc[i]) : wave_min_u32(acc[i]);
+    const int w = threadIdx.x / kWave;
+    if (__lane_id() == 0) {
+#pragma unroll
+        for (int i = 0; i < 4 * D; ++i)
+            s_r[w][i] = acc[i];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 * D) {
+        const int i = threadIdx.x;
+        uint32_t v = s_r[0][i];
+        for (int q = 1; q < kWaves; ++q)
+            v = (i & 1) ? (s_r[q][i] > v ? s_r[q][i] : v) : (s_r[q][i] < v ? s_r[q][i] : v);
+        child_boxes[2 * t * 2 * D + i] = v;
     }
 }
 
@@ -523,9 +596,11 @@ __global__ __launch_bounds__(kThreads) void k_soa_init(const int32_t *__restrict
 template <typename C, int D>
 __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict__ X, const uint32_t *__restrict__ I,
                                                      int64_t n, int jb, int h, Origin origin, C *__restrict__ tree_box,
+                                                     uint32_t *__restrict__ rel_box,
                                                      C *__restrict__ coords, int32_t *__restrict__ sidx,
                                                      uint32_t *__restrict__ leaf_org, uint32_t *__restrict__ leaf_ext,
-                                                     uint32_t *__restrict__ leaf_pack) {
+                                                     uint32_t *__restrict__ leaf_pack,
+                                                     uint64_t *__restrict__ split_hint) {
     constexpr int M = Bottom<D>::kSize;
     constexpr int NB = Bottom<D>::kNodes;
     constexpr int PER = M / kThreads;
@@ -537,6 +612,8 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
     __shared__ uint16_t s_dst[M];
     __shared__ uint32_t s_hist[kWaves][kNB];
     __shared__ uint32_t s_box[NB][D][2];
+    __shared__ uint32_t s_pick[kWaves][2];
+    __shared__ uint32_t s_cnt[kWaves][2];
 
     const int64_t S0 = (int64_t)kLeafSize << (h - jb);  // at most M
     const int64_t s0 = (int64_t)blockIdx.x * S0;
@@ -589,6 +666,8 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
             for (int k = 0; k < D; ++k) {
                 tree_box[(v * D + k) * 2 + 0] = (C)((int64_t)origin.v[k] + (int64_t)s_box[u][k][0]);
                 tree_box[(v * D + k) * 2 + 1] = (C)((int64_t)origin.v[k] + (int64_t)s_box[u][k][1]);
+                rel_box[(v * D + k) * 2 + 0] = s_box[u][k][0];
+                rel_box[(v * D + k) * 2 + 1] = s_box[u][k][1];
                 const uint32_t e = s_box[u][k][1] - s_box[u][k][0];
                 ext = e > ext ? e : ext;
             }
@@ -603,6 +682,121 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
         }
         if (l == h)
             break;
+        if (2 * nsub <= kWaves) {
+            // Few nodes: G = kWaves / nsub waves split each node together.
+            // Every wave runs the same number of passes (the most any node
+            // needs) so that the block barriers line up.
+            const int G = kWaves / nsub;
+            const int u = w / G, sw = w % G;
+            const int base = u * S;
+            const int cnt = cnt0 - base < S ? cnt0 - base : S;
+            const int half = cnt < S / 2 ? cnt : S / 2;
+            const int a = longest_axis<D>(&s_box[u][0][0]);
+            const uint32_t lo = s_box[u][a][0];
+            int passes_max = 0, passes = 0;
+            for (int uu = 0; uu < nsub; ++uu) {
+                const int b_u = uu * S;
+                const int c_u = cnt0 - b_u < S ? cnt0 - b_u : S;
+                const int h_u = c_u < S / 2 ? c_u : S / 2;
+                const int a_u = longest_axis<D>(&s_box[uu][0][0]);
+                const int p_u =
+                    h_u == c_u ? 0 : (int)((bit_length(s_box[uu][a_u][1] - s_box[uu][a_u][0]) + kB - 1) / kB);
+                passes_max = p_u > passes_max ? p_u : passes_max;
+                if (uu == u)
+                    passes = p_u;
+            }
+            // this wave's contiguous share of the node's points
+            const int chunk = ((cnt + G * kWave - 1) / (G * kWave)) * kWave;
+            const int c_begin = sw * chunk < cnt ? sw * chunk : cnt;
+            const int c_end = c_begin + chunk < cnt ? c_begin + chunk : cnt;
+            uint32_t prefix = 0, rank = (uint32_t)half;
+            for (int p = 0; p < passes_max; ++p) {
+                const bool act = p < passes;
+                const int shift = (passes - 1 - p) * kB;
+                for (int b = sw * kWave + lane; b < kNB; b += G * kWave)
+                    s_hist[u][b] = 0u;
+                __syncthreads();
+                if (act) {
+                    for (int i = c_begin + lane; i < c_end; i += kWave) {
+                        const uint64_t v = (uint64_t)(s_x[a][base + i] - lo);
+                        if ((v >> (shift + kB)) == (uint64_t)prefix)
+                            atomicAdd(&s_hist[u][(uint32_t)(v >> shift) & (kNB - 1)], 1u);
+                    }
+                }
+                __syncthreads();
+                if (act && sw == 0) {
+                    uint32_t c[kLaneBins];
+                    uint32_t mine = 0;
+#pragma unroll
+                    for (int b = 0; b < kLaneBins; ++b) {
+                        c[b] = s_hist[u][lane * kLaneBins + b];
+                        mine += c[b];
+                    }
+                    uint32_t cum = wave_incl_scan(mine) - mine;
+#pragma unroll
+                    for (int b = 0; b < kLaneBins; ++b) {
+                        if (cum <= rank && rank < cum + c[b]) {
+                            s_pick[u][0] = (uint32_t)(lane * kLaneBins + b);
+                            s_pick[u][1] = cum;
+                        }
+                        cum += c[b];
+                    }
+                }
+                __syncthreads();
+                if (act) {
+                    prefix = (prefix << kB) | s_pick[u][0];
+                    rank -= s_pick[u][1];
+                }
+            }
+            const uint32_t median = prefix, need_eq = rank;
+            const bool split_node = half != cnt;
+            if (split_node && sw == 0 && lane == 0)
+                split_hint[(1ll << l) + s0 / S + u] = ((uint64_t)(uint32_t)a << 32) | (uint64_t)(lo + median);
+            // counts of this wave's share, then stable destinations
+            uint32_t nl = 0, ne = 0;
+            if (split_node) {
+                for (int i0 = c_begin; i0 < c_end; i0 += kWave) {
+                    const int i = i0 + lane;
+                    const bool valid = i < c_end;
+                    const uint32_t v = valid ? s_x[a][base + i] - lo : 0u;
+                    nl += (uint32_t)__popcll(__ballot(valid && v < median));
+                    ne += (uint32_t)__popcll(__ballot(valid && v == median));
+                }
+            }
+            if (lane == 0) {
+                s_cnt[w][0] = nl;
+                s_cnt[w][1] = ne;
+            }
+            __syncthreads();
+            uint32_t run_l = 0, run_e = 0;
+            for (int q = u * G; q < w; ++q) {
+                run_l += s_cnt[q][0];
+                run_e += s_cnt[q][1];
+            }
+            for (int i0 = c_begin; i0 < c_end; i0 += kWave) {
+                const int i = i0 + lane;
+                const bool valid = i < c_end;
+                if (!split_node) {
+                    if (valid)
+                        s_dst[base + i] = (uint16_t)(base + i);
+                    continue;
+                }
+                const uint32_t v = valid ? s_x[a][base + i] - lo : 0u;
+                const bool less = valid && v < median;
+                const bool eq = valid && v == median;
+                const uint64_t ml = __ballot(less), me = __ballot(eq);
+                const uint32_t lbefore = run_l + (uint32_t)__popcll(ml & lanes_below());
+                const uint32_t ebefore = run_e + (uint32_t)__popcll(me & lanes_below());
+                run_l += (uint32_t)__popcll(ml);
+                run_e += (uint32_t)__popcll(me);
+                if (valid) {
+                    const bool left = less || (eq && ebefore < need_eq);
+                    const uint32_t left_before = lbefore + (ebefore < need_eq ? ebefore : need_eq);
+                    const uint32_t dst = left ? left_before : (uint32_t)half + ((uint32_t)i - left_before);
+                    s_dst[base + i] = (uint16_t)(base + dst);
+                }
+            }
+        } else {
         // each wave splits whole nodes: exact median, then stable destinations
         for (int u = w; u < nsub; u += kWaves) {
             const int base = u * S;
@@ -665,6 +859,8 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
                 rank -= below;
             }
             const uint32_t median = prefix, need_eq = rank;
+            if (lane == 0)
+                split_hint[(1ll << l) + s0 / S + u] = ((uint64_t)(uint32_t)a << 32) | (uint64_t)(lo + median);
             uint32_t run_l = 0, run_e = 0;
             for (int i0 = 0; i0 < cnt; i0 += kWave) {
                 const int i = i0 + lane;
@@ -686,6 +882,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
                     s_dst[base + i] = (uint16_t)(base + dst);
                 }
             }
+        }
         }
         __syncthreads();
         // apply the permutation through registers
@@ -742,15 +939,25 @@ inline int level_bits(int j) { return j <= kWideLevels ? 11 : 8; }
 
 template <typename C, int D, int BITS>
 void launch_level(const uint32_t *Xin, const uint32_t *Iin, uint32_t *Xout, uint32_t *Iout, int64_t n, int j, int h,
-                  int passes, const uint32_t *bj, uint32_t *bj1, uint32_t *hj, NodeSplit *split, uint32_t *cnt_less,
-                  uint32_t *cnt_eq, C *box, Origin origin, unsigned grid, unsigned tiles, hipStream_t s) {
-    for (int p = 0; p < passes; ++p)
-        hipLaunchKernelGGL((k_sel_hist<D, BITS>), dim3(grid), dim3(kThreads), 0, s, Xin, n, j, h, bj, hj, p);
-    hipLaunchKernelGGL((k_part_count<C, D, BITS>), dim3(grid), dim3(kThreads), 0, s, Xin, n, j, h, bj, bj1, hj, split,
-                       cnt_less, cnt_eq, box, origin);
-    hipLaunchKernelGGL(k_part_scan, dim3(2), dim3(kThreads), 0, s, cnt_less, cnt_eq, (int)tiles);
+                  int passes, const uint32_t *bj, uint32_t *bj1, uint32_t *hj, SelectState *state,
+                  NodeSplit *split, uint32_t *cnt_less, uint32_t *cnt_eq, uint32_t *tile_box, C *box,
+                  uint32_t *rel_box, uint64_t *split_hint, Origin origin,
+                  unsigned grid, unsigned tiles, hipStream_t s) {
+    // tiles per histogram workgroup: up to 8, never more than a node holds
+    const int64_t node_tiles = ((int64_t)kLeafSize << (h - j)) / kTile;
+    const int per = node_tiles < 8 ? (int)node_tiles : 8;
+    const unsigned hgrid = (unsigned)((tiles + per - 1) / per);
+    for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL((k_sel_hist<D, BITS>), dim3(hgrid), dim3(kThreads), 0, s, Xin, n, j, h, bj, hj, p, state,
+                           per);
+        hipLaunchKernelGGL((k_sel_pick<D, BITS>), dim3(1u << j), dim3(kThreads), 0, s, n, j, h, bj, hj, p, state);
+    }
+    hipLaunchKernelGGL((k_part_count<C, D, BITS>), dim3(grid), dim3(kThreads), 0, s, Xin, n, j, h, bj, state,
+                       split, cnt_less, cnt_eq, box, rel_box, split_hint, origin);
+    hipLaunchKernelGGL(k_part_scan, dim3(2), dim3(kScanThreads), 0, s, cnt_less, cnt_eq, (int)tiles);
     hipLaunchKernelGGL((k_part_scatter<D>), dim3(grid), dim3(kThreads), 0, s, Xin, Iin, Xout, Iout, n, j, h, split,
-                       cnt_less, cnt_eq, bj1);
+                       cnt_less, cnt_eq, tile_box);
+    hipLaunchKernelGGL((k_box_reduce<D>), dim3(1u << j), dim3(kThreads), 0, s, n, j, h, tile_box, bj1);
 }
 
 template <typename C, int D>
@@ -770,7 +977,9 @@ dpc_status build_kd(const int32_t *points, Workspace &ws, Index &ix) {
     C *coords, *box;
     DPC_TRY(ws.alloc(&coords, (size_t)n * D));
     DPC_TRY(ws.alloc(&box, (size_t)2 * ix.n_leaves * 2 * D));
+    DPC_TRY(ws.alloc(&ix.rbox, (size_t)2 * ix.n_leaves * 2 * D));
     DPC_TRY(ws.alloc(&ix.sidx, n));
+    DPC_TRY(ws.alloc(&ix.split, (size_t)ix.n_leaves));
     DPC_TRY(ws.alloc(&ix.leaf_org, (size_t)ix.n_leaves * D));
     DPC_TRY(ws.alloc(&ix.leaf_ext, (size_t)ix.n_leaves));
     DPC_TRY(ws.alloc(&ix.leaf_pack, (size_t)n * ((D + 1) / 2)));
@@ -798,11 +1007,16 @@ dpc_status build_kd(const int32_t *points, Workspace &ws, Index &ix) {
         }
         uint32_t *nboxes, *hist, *cnt_less, *cnt_eq;
         NodeSplit *split;
+        SelectState *state;
+        const int64_t max_nodes = 1ll << (jb - 1);  // nodes of the deepest top level
         DPC_TRY(ws.alloc(&nboxes, (size_t)(2ll << jb) * 2 * D));
         DPC_TRY(ws.alloc(&hist, (size_t)(hist_words > 0 ? hist_words : 1)));
-        DPC_TRY(ws.alloc(&split, (size_t)1 << (jb - 1)));
+        DPC_TRY(ws.alloc(&split, (size_t)max_nodes));
+        DPC_TRY(ws.alloc(&state, (size_t)max_nodes));
         DPC_TRY(ws.alloc(&cnt_less, (size_t)tiles));
         DPC_TRY(ws.alloc(&cnt_eq, (size_t)tiles));
+        uint32_t *tile_box;
+        DPC_TRY(ws.alloc(&tile_box, (size_t)tiles * 4 * D));
         if (hist_words > 0)
             hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(hist_words, kThreads)), dim3(kThreads), 0, s, hist,
                                hist_words, 0u);
@@ -815,11 +1029,11 @@ dpc_status build_kd(const int32_t *points, Workspace &ws, Index &ix) {
             const int bits = level_bits(j);
             const int passes = (wbits + bits - 1) / bits;
             if (bits == 11)
-                launch_level<C, D, 11>(Xin, Iin, Xout, Iout, n, j, h, passes, bj, bj1, hist + hist_off[j], split,
-                                       cnt_less, cnt_eq, box, origin, grid, (unsigned)tiles, s);
+                launch_level<C, D, 11>(Xin, Iin, Xout, Iout, n, j, h, passes, bj, bj1, hist + hist_off[j], state,
+                                       split, cnt_less, cnt_eq, tile_box, box, ix.rbox, ix.split, origin, grid, (unsigned)tiles, s);
             else
-                launch_level<C, D, 8>(Xin, Iin, Xout, Iout, n, j, h, passes, bj, bj1, hist + hist_off[j], split,
-                                      cnt_less, cnt_eq, box, origin, grid, (unsigned)tiles, s);
+                launch_level<C, D, 8>(Xin, Iin, Xout, Iout, n, j, h, passes, bj, bj1, hist + hist_off[j], state,
+                                      split, cnt_less, cnt_eq, tile_box, box, ix.rbox, ix.split, origin, grid, (unsigned)tiles, s);
             DPC_HIP(hipGetLastError());
             uint32_t *t = Xin;
             Xin = Xout;
@@ -832,7 +1046,7 @@ dpc_status build_kd(const int32_t *points, Workspace &ws, Index &ix) {
         IA = Iin;
     }
     hipLaunchKernelGGL((k_bottom<C, D>), dim3((unsigned)(1ll << jb)), dim3(kThreads), 0, s, XA, IA, n, jb, h, origin,
-                       box, coords, ix.sidx, ix.leaf_org, ix.leaf_ext, ix.leaf_pack);
+                       box, ix.rbox, coords, ix.sidx, ix.leaf_org, ix.leaf_ext, ix.leaf_pack, ix.split);
     DPC_HIP(hipGetLastError());
     return DPC_OK;
 }

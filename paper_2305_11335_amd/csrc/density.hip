@@ -52,9 +52,10 @@ struct Narrow {
 // Points of one leaf within distance^2 T of x.  The leaf's coordinates are
 // wave-uniform (scalar loads); a batch of kBatch points is loaded before any
 // is used so that the loads overlap.
-template <typename C, int D>
+template <typename C, int D, int kMaxBatch = 8>
 __device__ inline int32_t count_within(const C (&x)[D], const C *__restrict__ p, int count, C T) {
-    constexpr int kBatch = D <= 2 ? 8 : (D <= 4 ? 4 : 2);  // within the scalar registers
+    constexpr int kFit = D <= 2 ? 8 : (D <= 4 ? 4 : 2);  // within the scalar registers
+    constexpr int kBatch = kFit < kMaxBatch ? kFit : kMaxBatch;
     int32_t c = 0;
     int t = 0;
     for (; t + kBatch <= count; t += kBatch) {
@@ -142,7 +143,7 @@ __device__ inline void box_dist2_clamped(const int32_t (&xi)[D], const uint32_t 
     dmax2 = mx;
 }
 
-template <typename C, int D, bool STATS>
+template <typename C, int D, bool STATS, bool INTBOX>
 __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coords, const C *__restrict__ box,
                                                       const uint32_t *__restrict__ rbox, int64_t n, int height, C T,
                                                       C r, Narrow nw,
@@ -199,84 +200,157 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
     const uint32_t first_leaf = 1u << height;
     uint32_t v = home >> (hd - sd);
     int depth = sd;
-    for (;;) {
-        int64_t start, count;
-        node_range(v, depth, height, n, start, count);
-        bool descend = false;
-        if (count > 0) {
+
+    // Points of leaf v (positions [start, start + count)) within the radius,
+    // for the lanes to which the leaf is partial.
+    auto leaf_count = [&](uint32_t leaf, int64_t start, int64_t count, bool partial) {
+        if (STATS && __ballot(partial) != 0)
+            w_points += (uint64_t)count;
+        if (!partial)
+            return;
+        if (STATS)
+            n_pairs += (uint64_t)count;
+        const uint32_t c = leaf - first_leaf;
+        bool narrow = false;
+        if constexpr (kPacked)
+            narrow = (int32_t)nw.ext[c] <= nw.limit;
+        if (narrow) {
+            uint32_t qw[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const int32_t a = clamp_i32(xi[2 * w] - (int32_t)nw.org[(size_t)c * D + 2 * w], -nw.M, nw.R);
+                const int32_t b =
+                    2 * w + 1 < D ? clamp_i32(xi[2 * w + 1] - (int32_t)nw.org[(size_t)c * D + 2 * w + 1], -nw.M, nw.R)
+                                  : 0;
+                qw[w] = ((uint32_t)a & 0xFFFFu) | ((uint32_t)b << 16);
+            }
+            cnt += count_within_packed<W>(qw, nw.pack + start * W, (int)count, nw.T);
+        } else {
+            // (rare next to narrow leaves: a small batch keeps registers for the walk)
+            cnt += count_within<C, D, INTBOX ? 2 : 8>(x, coords + start * D, (int)count, T);
+        }
+    };
+    // Classifies the current node for this lane (unless it settled above);
+    // returns whether the node is partial to it.
+    auto classify = [&](bool outside, bool inside, int64_t count) {
+        if (outside) {
+            settled = depth;
+        } else if (inside) {
+            cnt += (int32_t)count;
+            settled = depth;
             if (STATS)
-                ++w_nodes;
-            bool partial = false;
-            if (settled >= depth) {
-                settled = INT_MAX;
+                n_contained += (uint64_t)count;
+        } else {
+            return true;
+        }
+        return false;
+    };
+
+    if constexpr (INTBOX) {
+        // Integer boxes, with the next boxes loaded ahead: while node v is
+        // tested, both its children's boxes (adjacent in memory) are already
+        // on their way, and a left child keeps its sibling's box for the
+        // step after it.
+        constexpr int B = 2 * D;
+        uint32_t cur[B], sib[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            cur[i] = rbox[(size_t)v * B + i];
+            sib[i] = 0u;
+        }
+        for (;;) {
+            int64_t start, count;
+            node_range(v, depth, height, n, start, count);
+            const bool internal = v < first_leaf;
+            uint32_t kids[2 * B];
+            if (internal) {
+#pragma unroll
+                for (int i = 0; i < 2 * B; ++i)
+                    kids[i] = rbox[(size_t)(2 * v) * B + i];
+            }
+            bool descend = false;
+            if (count > 0) {
                 if (STATS)
-                    ++n_nodes;
-                bool outside, inside;
-                if (kPacked && nw.limit >= 0) {
+                    ++w_nodes;
+                bool partial = false;
+                if (settled >= depth) {
+                    settled = INT_MAX;
+                    if (STATS)
+                        ++n_nodes;
                     int32_t dmin2, dmax2;
-                    box_dist2_clamped<D>(xi, rbox + (size_t)v * 2 * D, nw.M, dmin2, dmax2);
-                    outside = dmin2 > nw.T;
-                    inside = dmax2 <= nw.T;
-                } else {
+                    box_dist2_clamped<D>(xi, cur, nw.M, dmin2, dmax2);
+                    partial = classify(dmin2 > nw.T, dmax2 <= nw.T, count);
+                }
+                if (!internal)
+                    leaf_count(v, start, count, partial);
+                else
+                    descend = __ballot(partial) != 0;
+            }
+            if (descend) {
+                v <<= 1;
+                ++depth;
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    cur[i] = kids[i];
+                    sib[i] = kids[B + i];
+                }
+                continue;
+            }
+            if (depth > sd && (v & 1u) == 0) {
+                // a left child: its sibling's box came with it
+                v += 1;
+#pragma unroll
+                for (int i = 0; i < B; ++i)
+                    cur[i] = sib[i];
+                continue;
+            }
+            while (depth > sd && (v & 1u)) {
+                v >>= 1;
+                --depth;
+            }
+            if (depth == sd)
+                break;
+            v += 1;
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                cur[i] = rbox[(size_t)v * B + i];
+        }
+    } else {
+        for (;;) {
+            int64_t start, count;
+            node_range(v, depth, height, n, start, count);
+            bool descend = false;
+            if (count > 0) {
+                if (STATS)
+                    ++w_nodes;
+                bool partial = false;
+                if (settled >= depth) {
+                    settled = INT_MAX;
+                    if (STATS)
+                        ++n_nodes;
                     C dmin2, dmax2;
                     box_dist2<C, D>(x, box + (size_t)v * 2 * D, dmin2, dmax2);
-                    outside = dmin2 > T;
-                    inside = dmax2 <= T;
+                    partial = classify(dmin2 > T, dmax2 <= T, count);
                 }
-                if (outside) {
-                    settled = depth;
-                } else if (inside) {
-                    cnt += (int32_t)count;
-                    settled = depth;
-                    if (STATS)
-                        n_contained += (uint64_t)count;
-                } else {
-                    partial = true;
-                }
+                if (v >= first_leaf)
+                    leaf_count(v, start, count, partial);
+                else
+                    descend = __ballot(partial) != 0;
             }
-            if (v >= first_leaf) {
-                if (STATS && __ballot(partial) != 0)
-                    w_points += (uint64_t)count;
-                if (partial) {
-                    if (STATS)
-                        n_pairs += (uint64_t)count;
-                    const uint32_t c = v - first_leaf;
-                    bool narrow = false;
-                    if constexpr (kPacked)
-                        narrow = (int32_t)nw.ext[c] <= nw.limit;
-                    if (narrow) {
-                        uint32_t qw[W];
-#pragma unroll
-                        for (int w = 0; w < W; ++w) {
-                            const int32_t a = clamp_i32(xi[2 * w] - (int32_t)nw.org[(size_t)c * D + 2 * w], -nw.M, nw.R);
-                            const int32_t b = 2 * w + 1 < D ? clamp_i32(xi[2 * w + 1] -
-                                                                            (int32_t)nw.org[(size_t)c * D + 2 * w + 1],
-                                                                        -nw.M, nw.R)
-                                                            : 0;
-                            qw[w] = ((uint32_t)a & 0xFFFFu) | ((uint32_t)b << 16);
-                        }
-                        cnt += count_within_packed<W>(qw, nw.pack + start * W, (int)count, nw.T);
-                    } else {
-                        cnt += count_within<C, D>(x, coords + start * D, (int)count, T);
-                    }
-                }
-            } else {
-                descend = __ballot(partial) != 0;
+            if (descend) {
+                v <<= 1;
+                ++depth;
+                continue;
             }
+            // next node of the walk below the start node
+            while (depth > sd && (v & 1u)) {
+                v >>= 1;
+                --depth;
+            }
+            if (depth == sd)
+                break;
+            v += 1;
         }
-        if (descend) {
-            v <<= 1;
-            ++depth;
-            continue;
-        }
-        // next node of the walk below the start node
-        while (depth > sd && (v & 1u)) {
-            v >>= 1;
-            --depth;
-        }
-        if (depth == sd)
-            break;
-        v += 1;
     }
     if (valid) {
         srho[q] = cnt;
@@ -291,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
     }
 }
 
-template <typename C, bool STATS>
+template <typename C, bool STATS, bool INTBOX>
 dpc_status launch_typed(const Index &ix, C T, C r, const Narrow &nw, int32_t *srho, int32_t *rho_out,
                         int64_t *counters, hipStream_t s) {
     const C *coords = static_cast<const C *>(ix.coords);
@@ -300,7 +374,8 @@ dpc_status launch_typed(const Index &ix, C T, C r, const Narrow &nw, int32_t *sr
     switch (ix.d) {
 #define DPC_DENSITY_CASE(DD)                                                                                    \
     case DD:                                                                                                    \
-        hipLaunchKernelGGL((k_density<C, DD, STATS>), grid, block, 0, s, coords, box, ix.rbox, ix.n, ix.height, T, \
+        hipLaunchKernelGGL((k_density<C, DD, STATS, INTBOX && DD <= 4>), grid, block, 0, s, coords, box, ix.rbox,  \
+                           ix.n, ix.height, T,                                                                  \
                            r, nw, srho, ix.sidx, rho_out, counters);                                            \
         break;
         DPC_DENSITY_CASE(1)
@@ -350,11 +425,15 @@ dpc_status launch_density(const Index &ix, int64_t T, int32_t *srho, int32_t *rh
         // every squared distance is below 2^53, so a larger threshold acts like 2^53
         const double t = T >= (1ll << 53) ? 9007199254740992.0 : (double)T;
         const double rr = (double)r;
-        return counters ? launch_typed<double, true>(ix, t, rr, nw, srho, rho_out, counters, s)
-                        : launch_typed<double, false>(ix, t, rr, nw, srho, rho_out, nullptr, s);
+        // integer boxes when every clamped gap fits (then T < M^2 <= R^2)
+        if (nw.limit >= 0)
+            return counters ? launch_typed<double, true, true>(ix, t, rr, nw, srho, rho_out, counters, s)
+                            : launch_typed<double, false, true>(ix, t, rr, nw, srho, rho_out, nullptr, s);
+        return counters ? launch_typed<double, true, false>(ix, t, rr, nw, srho, rho_out, counters, s)
+                        : launch_typed<double, false, false>(ix, t, rr, nw, srho, rho_out, nullptr, s);
     }
-    return counters ? launch_typed<int64_t, true>(ix, T, r, nw, srho, rho_out, counters, s)
-                    : launch_typed<int64_t, false>(ix, T, r, nw, srho, rho_out, nullptr, s);
+    return counters ? launch_typed<int64_t, true, false>(ix, T, r, nw, srho, rho_out, counters, s)
+                    : launch_typed<int64_t, false, false>(ix, T, r, nw, srho, rho_out, nullptr, s);
 }
 
 }  // namespace dpc

@@ -228,3 +228,76 @@ def clustered_small(seed: int, n: int, d: int, span: int = 1 << 20, k: int = 5,
     parts = _gaussian_clusters(rng, counts, centers, np.full((k, 1), sd_frac * span))
     parts.append(rng.integers(0, span, size=(n_noise, d)).astype(np.float64))
     return _finish(rng, parts, 0, span, clip=True)
+
+
+# ---------------------------------------------------------------------------
+# many independent instances (batched and served workloads)
+
+def _dcut_for_median_rho(points: np.ndarray, target: int, rng, sample: int = 256) -> float:
+    """A radius giving a median density of about ``target`` (self included):
+    the median distance from a sample of points to their ``target``-th
+    nearest neighbour (counting the point itself), from scipy's k-d tree.
+    This only sets an input parameter; no output is derived from it."""
+    from scipy.spatial import cKDTree
+
+    n = points.shape[0]
+    k = min(target, n)
+    idx = rng.choice(n, size=min(sample, n), replace=False)
+    dist, _ = cKDTree(points.astype(np.float64)).query(points[idx].astype(np.float64), k=k)
+    dk = dist[:, -1] if dist.ndim == 2 else dist
+    return float(max(np.median(dk), 1.0))
+
+
+def gen_blob_instance(rng, n: int, d: int, span: int = 1 << 20, noise: float = 0.05) -> np.ndarray:
+    """2-50 isotropic Gaussian blobs (sd span/50, equal weights) plus uniform
+    noise, rounded and clipped to [0, span)^d."""
+    k = int(rng.integers(2, 51))
+    n_noise = int(round(noise * n))
+    centers = rng.uniform(0, span, size=(k, d))
+    counts = rng.multinomial(n - n_noise, np.full(k, 1.0 / k))
+    parts = _gaussian_clusters(rng, counts, centers, np.full((k, 1), span / 50.0))
+    parts.append(rng.integers(0, span, size=(n_noise, d)).astype(np.float64))
+    return _finish(rng, parts, 0, span, clip=True)
+
+
+def gen_uniform_instance(rng, n: int, d: int, span: int = 1 << 20) -> np.ndarray:
+    pts = rng.integers(0, span, size=(n, d), dtype=np.int64)
+    return np.ascontiguousarray(pts.astype(np.int32))
+
+
+def batch_instances(seed: int = 4, count: int = 512, n_lo: int = 1_000, n_hi: int = 200_000,
+                    dims=(2, 3, 5, 8), median_rho: int = 20) -> list:
+    """The batched workload: ``count`` independent instances, n log-uniform in
+    [n_lo, n_hi], d uniform over ``dims``, Gaussian-blob data (2-50 blobs, 5%
+    noise, [0, 2^20)^d), d_cut for a median density of about 20, rho_min 5,
+    delta_min 4 d_cut.  Instance i draws from seed (seed, i)."""
+    out = []
+    for i in range(count):
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, i])))
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        d = int(dims[int(rng.integers(0, len(dims)))])
+        pts = gen_blob_instance(rng, n, d)
+        d_cut = _dcut_for_median_rho(pts, median_rho, rng)
+        out.append(Instance(name=f"batch{seed}_{i}", points=pts, d_cut=d_cut, rho_min=5,
+                            delta_min=4.0 * d_cut, seed=seed))
+    return out
+
+
+def served_instances(seed: int = 5, count: int = 64, n_lo: int = 1_000, n_hi: int = 1_000_000, d: int = 3,
+                     median_rho: int = 20) -> list:
+    """The request pool of the served workload: n log-uniform in [n_lo, n_hi],
+    d = 3, each uniform or Gaussian blobs with probability 1/2, int32 in
+    [0, 2^20)^3; parameters as in the batched workload.  A request stream
+    draws its requests from this pool."""
+    out = []
+    for i in range(count):
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, i])))
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        if rng.random() < 0.5:
+            pts = gen_uniform_instance(rng, n, d)
+        else:
+            pts = gen_blob_instance(rng, n, d)
+        d_cut = _dcut_for_median_rho(pts, median_rho, rng)
+        out.append(Instance(name=f"served{seed}_{i}", points=pts, d_cut=d_cut, rho_min=5,
+                            delta_min=4.0 * d_cut, seed=seed))
+    return out

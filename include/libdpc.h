@@ -166,6 +166,42 @@ DPC_API int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, i
             int32_t *label, hipStream_t stream);
 
 /*
+ * One independent clustering problem of a batch: the arguments and output
+ * arrays of dpc_run, plus the instance's own status (written).
+ */
+typedef struct {
+    const int32_t *points; /* int32 [n][d] device */
+    int64_t n;
+    int32_t d;
+    double d_cut;
+    int32_t rho_min;
+    double delta_min;
+    int32_t *rho;          /* int32 [n] device, written */
+    int32_t *dep;          /* int32 [n] device, written */
+    int64_t *delta2;       /* int64 [n] device, written */
+    int32_t *label;        /* int32 [n] device, written */
+    int32_t status;        /* written: the status dpc_run would return for this instance */
+} dpc_instance;
+
+/*
+ * The whole method on many independent instances at once (sizes and
+ * dimensions may differ).  Instances of one dimension and one arithmetic
+ * share every launch: each step runs once over all of them, so the number of
+ * kernel launches does not grow with the number of instances.  Every
+ * instance's outputs are bit-identical to those of dpc_run with the same
+ * arguments.
+ *   instances  host array of count records; pointers in them are device
+ *              pointers.  Each record's status is set: an invalid instance
+ *              (as dpc_run would reject it) or one out of range is skipped.
+ *   flags      0 or DPC_SKIP_NOISE_DEPENDENTS (applies to every instance).
+ * Returns DPC_OK if every instance succeeded, otherwise the first failing
+ * instance's status (or a runtime error, after which outputs are
+ * unspecified).  Reads back the coordinate bounds of each dimension's
+ * instances once (synchronising the stream).
+ */
+DPC_API int dpc_batch_run(dpc_instance *instances, int32_t count, uint32_t flags, hipStream_t stream);
+
+/*
  * Diagnostics: copies the measurements of the calling thread's most recent
  * dpc_run made with DPC_TIME_STAGES or DPC_COUNT_WORK into *out, waiting for
  * that call's recorded events first.  DPC_ERR_INVALID_ARG if out is NULL or

@@ -7,12 +7,14 @@ include/libdpc.h; this package is its thin Python binding.  See
 """
 from ._binding import (  # noqa: F401
     DPCError,
+    Instance,
     EXPORTED,
     INF,
     LIB_PATH,
     SKIP_NOISE_DEPENDENTS,
     STAGES,
     WORK_FIELDS,
+    batch_run,
     cluster,
     density,
     dependent,

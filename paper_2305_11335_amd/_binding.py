@@ -20,8 +20,8 @@ COUNT_WORK = 4
 INF = (1 << 63) - 1
 STAGES = ("index", "density", "priority", "dependent", "labels")
 
-EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_last_stats", "dpc_status_str",
-            "dpc_square_threshold")
+EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_batch_run", "dpc_last_stats",
+            "dpc_status_str", "dpc_square_threshold")
 
 
 class Stats(ctypes.Structure):
@@ -34,6 +34,14 @@ class Stats(ctypes.Structure):
 
 WORK_FIELDS = ("density_pairs", "density_nodes", "density_contained", "dependent_pairs", "dependent_nodes",
                "density_wave_nodes", "density_wave_points", "dependent_wave_nodes", "dependent_wave_points")
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("d_cut", ctypes.c_double), ("rho_min", ctypes.c_int32), ("delta_min", ctypes.c_double),
+                ("rho", ctypes.c_void_p), ("dep", ctypes.c_void_p), ("delta2", ctypes.c_void_p),
+                ("label", ctypes.c_void_p), ("status", ctypes.c_int32)]
+
 
 _lib = None
 
@@ -65,6 +73,8 @@ def load():
     lib.dpc_status_str.restype = ctypes.c_char_p
     lib.dpc_square_threshold.argtypes = [dbl, i32, P]
     lib.dpc_square_threshold.restype = ctypes.c_int
+    lib.dpc_batch_run.argtypes = [ctypes.POINTER(Instance), ctypes.c_int32, u32, P]
+    lib.dpc_batch_run.restype = ctypes.c_int
     lib.dpc_last_stats.argtypes = [ctypes.POINTER(Stats)]
     lib.dpc_last_stats.restype = ctypes.c_int
     _lib = lib
@@ -203,3 +213,32 @@ def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool =
     if st != OK:
         raise DPCError(st, "dpc_run")
     return rho, dep, delta2, label
+
+
+def batch_run(problems, skip_noise: bool = False, outs=None, stream=None, check: bool = True):
+    """Runs many independent instances in one call.
+
+    problems: sequence of (points, d_cut, rho_min, delta_min) with points an
+    int32 [n, d] device tensor.  Returns [(rho, dep, delta2, label), ...] and
+    the per-instance statuses.  outs (optional) supplies the output tensors.
+    With check, a failing instance raises."""
+    torch = _torch()
+    recs = (Instance * max(len(problems), 1))()
+    results = []
+    for i, (points, d_cut, rho_min, delta_min) in enumerate(problems):
+        n, d = _check_points(points)
+        dev = points.device
+        o = outs[i] if outs is not None else (None, None, None, None)
+        rho = _out(o[0], n, torch.int32, dev)
+        dep = _out(o[1], n, torch.int32, dev)
+        delta2 = _out(o[2], n, torch.int64, dev)
+        label = _out(o[3], n, torch.int32, dev)
+        recs[i] = Instance(_ptr(points).value, n, d, float(d_cut), int(rho_min), float(delta_min), _ptr(rho).value,
+                           _ptr(dep).value, _ptr(delta2).value, _ptr(label).value, -1)
+        results.append((rho, dep, delta2, label))
+    flags = SKIP_NOISE_DEPENDENTS if skip_noise else 0
+    st = load().dpc_batch_run(recs, len(problems), flags, _stream(stream))
+    statuses = [recs[i].status for i in range(len(problems))]
+    if check and st != OK:
+        raise DPCError(st, "dpc_batch_run")
+    return results, statuses

@@ -194,6 +194,55 @@ dpc_status delta_threshold(double delta_min, int64_t *Td) {
     return square_threshold(delta_min, true, Td);
 }
 
+// Checks one instance's arguments and fills its job (flags as for dpc_run).
+dpc_status make_job(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
+                    uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2, int32_t *label, Job &J) {
+    if (bad_shape(n, d) || std::isnan(d_cut) || d_cut < 0.0 || rho_min < 0)
+        return DPC_ERR_INVALID_ARG;
+    int64_t Td;
+    if (delta_threshold(delta_min, &Td) != DPC_OK)
+        return DPC_ERR_INVALID_ARG;
+    if (n > 0 && (points == nullptr || rho == nullptr || dep == nullptr || delta2 == nullptr || label == nullptr))
+        return DPC_ERR_INVALID_ARG;
+    J.points = points;
+    J.n = n;
+    DPC_TRY(square_threshold(d_cut, false, &J.T));
+    J.rho_min = rho_min;
+    J.Td = Td;
+    J.dep_rho_min = (flags & DPC_SKIP_NOISE_DEPENDENTS) ? rho_min : std::numeric_limits<int32_t>::min();
+    J.rho = rho;
+    J.dep = dep;
+    J.delta2 = delta2;
+    J.label = label;
+    return DPC_OK;
+}
+
+// The whole method on one group (instances of one dimension and one
+// arithmetic), every step once for all of them.
+dpc_status run_group(const std::vector<Job> &jobs, int d, Arith arith, RunRecorder *rec, int64_t *counters,
+                     Workspace &ws) {
+    hipStream_t stream = ws.stream;
+    Index ix;
+    DPC_TRY(build_group(jobs, d, arith, ws, ix));
+    if (rec)
+        DPC_TRY(rec->mark(DPC_STAGE_INDEX));
+    int32_t *srho;
+    DPC_TRY(ws.alloc(&srho, (size_t)ix.positions));
+    DPC_TRY(launch_density(ix, srho, counters, stream));
+    if (rec)
+        DPC_TRY(rec->mark(DPC_STAGE_DENSITY));
+    DPC_TRY(build_priority(srho, false, ws, ix));
+    if (rec)
+        DPC_TRY(rec->mark(DPC_STAGE_PRIORITY));
+    DPC_TRY(launch_dependent(ix, counters, stream));
+    if (rec)
+        DPC_TRY(rec->mark(DPC_STAGE_DEPENDENT));
+    DPC_TRY(launch_group_labels(ix, ws));
+    if (rec)
+        DPC_TRY(rec->mark(DPC_STAGE_LABELS));
+    return DPC_OK;
+}
+
 }  // namespace
 }  // namespace dpc
 
@@ -224,14 +273,19 @@ int dpc_density(const int32_t *points, int64_t n, int32_t d, double d_cut, int32
         return DPC_ERR_INVALID_ARG;
     if (n == 0)
         return DPC_OK;
-    int64_t T;
-    DPC_TRY(square_threshold(d_cut, false, &T));
+    Job J;
+    J.points = points;
+    J.n = n;
+    J.rho = rho;
+    DPC_TRY(square_threshold(d_cut, false, &J.T));
     Workspace ws(stream);
+    std::vector<Job> jobs{J};
+    DPC_TRY(job_bounds(jobs, d, ws, nullptr));
     Index ix;
-    DPC_TRY(build_index(points, n, d, T, ws, ix));
+    DPC_TRY(build_group(jobs, d, job_arith(jobs[0], d), ws, ix));
     int32_t *srho;
-    DPC_TRY(ws.alloc(&srho, n));
-    return launch_density(ix, T, srho, rho, nullptr, stream);
+    DPC_TRY(ws.alloc(&srho, (size_t)ix.positions));
+    return launch_density(ix, srho, nullptr, stream);
 }
 
 int dpc_dependent(const int32_t *points, int64_t n, int32_t d, const int32_t *rho, int32_t rho_min, int32_t *dep,
@@ -242,12 +296,20 @@ int dpc_dependent(const int32_t *points, int64_t n, int32_t d, const int32_t *rh
         return DPC_ERR_INVALID_ARG;
     if (n == 0)
         return DPC_OK;
+    Job J;
+    J.points = points;
+    J.n = n;
+    J.rho = const_cast<int32_t *>(rho);  // read only here
+    J.dep = dep;
+    J.delta2 = delta2;
+    J.dep_rho_min = rho_min > 0 ? rho_min : std::numeric_limits<int32_t>::min();
     Workspace ws(stream);
+    std::vector<Job> jobs{J};
+    DPC_TRY(job_bounds(jobs, d, ws, nullptr));
     Index ix;
-    DPC_TRY(build_index(points, n, d, 0, ws, ix));
-    DPC_TRY(build_priority(nullptr, rho, ws, ix));
-    const int32_t skip_below = rho_min > 0 ? rho_min : std::numeric_limits<int32_t>::min();
-    return launch_dependent(ix, skip_below, dep, delta2, nullptr, stream);
+    DPC_TRY(build_group(jobs, d, job_arith(jobs[0], d), ws, ix));
+    DPC_TRY(build_priority(nullptr, true, ws, ix));
+    return launch_dependent(ix, nullptr, stream);
 }
 
 int dpc_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2, int32_t rho_min,
@@ -268,16 +330,12 @@ int dpc_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t
 int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
             uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2, int32_t *label, hipStream_t stream) {
     const uint32_t known = DPC_SKIP_NOISE_DEPENDENTS | DPC_TIME_STAGES | DPC_COUNT_WORK;
-    if (bad_shape(n, d) || std::isnan(d_cut) || d_cut < 0.0 || rho_min < 0 || (flags & ~known))
+    if (flags & ~known)
         return DPC_ERR_INVALID_ARG;
-    int64_t T, Td;
-    if (delta_threshold(delta_min, &Td) != DPC_OK)
-        return DPC_ERR_INVALID_ARG;
-    if (n > 0 && (points == nullptr || rho == nullptr || dep == nullptr || delta2 == nullptr || label == nullptr))
-        return DPC_ERR_INVALID_ARG;
+    Job J;
+    DPC_TRY(make_job(points, n, d, d_cut, rho_min, delta_min, flags, rho, dep, delta2, label, J));
     if (n == 0)
         return DPC_OK;
-    DPC_TRY(square_threshold(d_cut, false, &T));
     RunRecorder rec(flags, stream);
     DPC_TRY(rec.begin());
     Workspace ws(stream);
@@ -287,24 +345,65 @@ int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t r
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kWave), 0, stream, counters);
         DPC_HIP(hipGetLastError());
     }
-    Index ix;
-    DPC_TRY(build_index(points, n, d, T, ws, ix));
-    DPC_TRY(rec.mark(DPC_STAGE_INDEX));
-    int32_t *srho;
-    DPC_TRY(ws.alloc(&srho, n));
-    DPC_TRY(launch_density(ix, T, srho, rho, counters, stream));
-    DPC_TRY(rec.mark(DPC_STAGE_DENSITY));
-    DPC_TRY(build_priority(srho, nullptr, ws, ix));
-    DPC_TRY(rec.mark(DPC_STAGE_PRIORITY));
-    const int32_t dep_rho_min = (flags & DPC_SKIP_NOISE_DEPENDENTS) ? rho_min : std::numeric_limits<int32_t>::min();
-    DPC_TRY(launch_dependent(ix, dep_rho_min, dep, delta2, counters, stream));
-    DPC_TRY(rec.mark(DPC_STAGE_DEPENDENT));
-    DPC_TRY(launch_cluster(n, rho, dep, delta2, rho_min, Td, false, label, ws));
-    DPC_TRY(rec.mark(DPC_STAGE_LABELS));
+    std::vector<Job> jobs{J};
+    DPC_TRY(job_bounds(jobs, d, ws, nullptr));
+    DPC_TRY(run_group(jobs, d, job_arith(jobs[0], d), &rec, counters, ws));
     if (counters)
         DPC_TRY(rec.read_counters(counters));
     rec.commit();
     return DPC_OK;
+}
+
+int dpc_batch_run(dpc_instance *instances, int32_t count, uint32_t flags, hipStream_t stream) {
+    if (count < 0 || (count > 0 && instances == nullptr) || (flags & ~(uint32_t)DPC_SKIP_NOISE_DEPENDENTS))
+        return DPC_ERR_INVALID_ARG;
+    // checks, then groups by dimension
+    std::vector<std::vector<int>> by_d(kMaxDim + 1);
+    std::vector<Job> all(count);
+    int first_error = DPC_OK;
+    for (int i = 0; i < count; ++i) {
+        dpc_instance &q = instances[i];
+        q.status = make_job(q.points, q.n, q.d, q.d_cut, q.rho_min, q.delta_min, flags, q.rho, q.dep, q.delta2,
+                            q.label, all[i]);
+        if (q.status == DPC_OK && q.n > 0)
+            by_d[q.d].push_back(i);
+        if (q.status != DPC_OK && first_error == DPC_OK)
+            first_error = q.status;
+    }
+    for (int d = 1; d <= kMaxDim; ++d) {
+        if (by_d[d].empty())
+            continue;
+        std::vector<Job> jobs;
+        for (int i : by_d[d])
+            jobs.push_back(all[i]);
+        std::vector<int> bad;
+        {
+            Workspace ws(stream);
+            const dpc_status st = job_bounds(jobs, d, ws, &bad);
+            if (st != DPC_OK && st != DPC_ERR_RANGE)
+                return st;
+        }
+        for (int b : bad) {
+            instances[by_d[d][b]].status = DPC_ERR_RANGE;
+            if (first_error == DPC_OK)
+                first_error = DPC_ERR_RANGE;
+        }
+        // one group per arithmetic
+        for (int a = 0; a < 2; ++a) {
+            const Arith arith = a == 0 ? Arith::F64 : Arith::I64;
+            std::vector<Job> group;
+            for (size_t k = 0; k < jobs.size(); ++k) {
+                if (instances[by_d[d][k]].status != DPC_OK || job_arith(jobs[k], d) != arith)
+                    continue;
+                group.push_back(jobs[k]);
+            }
+            if (!group.empty()) {
+                Workspace ws(stream);
+                DPC_TRY(run_group(group, d, arith, nullptr, nullptr, ws));
+            }
+        }
+    }
+    return first_error;
 }
 
 int dpc_last_stats(dpc_stats *out) {

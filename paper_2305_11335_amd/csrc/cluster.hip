@@ -78,7 +78,65 @@ __global__ __launch_bounds__(kThreads) void k_roots(int64_t n, const int32_t *__
     label[i] = x;
 }
 
+// The same two steps for every instance of a group, on the instances' own
+// arrays (input order; the group's parent array holds instance i's parents
+// at positions [P_i, P_i + n_i)).  The edges come from the library's own
+// dependent step, so they form a forest by construction.
+__global__ __launch_bounds__(kThreads) void k_parent_group(const Inst *__restrict__ inst,
+                                                           const uint32_t *__restrict__ tile_inst,
+                                                           int32_t *__restrict__ par) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Inst &I = inst_of_tile(inst, tile_inst, ((int64_t)blockIdx.x * blockDim.x) / kTile);
+    const int64_t i = pos - I.P;
+    if (i >= I.n)
+        return;
+    int32_t p = (int32_t)i;
+    if (I.rho[i] >= I.rho_min && I.delta2[i] < I.Td)
+        p = I.dep[i];
+    par[pos] = p;
+}
+
+__global__ __launch_bounds__(kThreads) void k_roots_group(const Inst *__restrict__ inst,
+                                                          const uint32_t *__restrict__ tile_inst, int32_t *par_all) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Inst &I = inst_of_tile(inst, tile_inst, ((int64_t)blockIdx.x * blockDim.x) / kTile);
+    const int64_t i = pos - I.P;
+    if (i >= I.n)
+        return;
+    if (I.rho[i] < I.rho_min) {
+        I.label[i] = -1;
+        return;
+    }
+    int32_t *par = par_all + I.P;
+    int32_t x = (int32_t)i;
+    // a chain of strictly rising priorities has fewer than n edges
+    for (int64_t steps = 0; steps <= I.n; ++steps) {
+        const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == x)
+            break;
+        const int32_t g = __hip_atomic_load(&par[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (g == p) {
+            x = p;
+            break;
+        }
+        __hip_atomic_store(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = g;
+    }
+    I.label[i] = x;
+}
+
 }  // namespace
+
+dpc_status launch_group_labels(const Index &ix, Workspace &ws) {
+    hipStream_t s = ws.stream;
+    int32_t *par;
+    DPC_TRY(ws.alloc(&par, (size_t)ix.positions));
+    const dim3 grid(blocks_for(ix.positions, kThreads)), block(kThreads);
+    hipLaunchKernelGGL(k_parent_group, grid, block, 0, s, ix.inst, ix.tile_inst, par);
+    hipLaunchKernelGGL(k_roots_group, grid, block, 0, s, ix.inst, ix.tile_inst, par);
+    DPC_HIP(hipGetLastError());
+    return DPC_OK;
+}
 
 dpc_status launch_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2, int32_t rho_min,
                           int64_t Td, bool validate, int32_t *label, Workspace &ws) {

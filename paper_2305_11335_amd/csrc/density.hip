@@ -143,20 +143,57 @@ __device__ inline void box_dist2_clamped(const int32_t (&xi)[D], const uint32_t 
     dmax2 = mx;
 }
 
+// The group's arrays (position-, node- or leaf-indexed).
+template <typename C>
+struct DensityArrays {
+    const C *coords;
+    const C *box;
+    const uint32_t *rbox;
+    const uint32_t *org;
+    const uint32_t *ext;
+    const uint32_t *pack;
+    int32_t *srho;
+    const int32_t *sidx;
+};
+
 template <typename C, int D, bool STATS, bool INTBOX>
-__global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coords, const C *__restrict__ box,
-                                                      const uint32_t *__restrict__ rbox, int64_t n, int height, C T,
-                                                      C r, Narrow nw,
-                                                      int32_t *__restrict__ srho, const int32_t *__restrict__ sidx,
-                                                      int32_t *__restrict__ rho_out, int64_t *counters) {
+__global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ inst,
+                                                      const uint32_t *__restrict__ tile_inst, DensityArrays<C> G,
+                                                      int64_t *counters) {
     constexpr bool kPacked = std::is_same<C, double>::value;
     constexpr int W = (D + 1) / 2;
     uint64_t n_pairs = 0, n_nodes = 0, n_contained = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
-    const int64_t q0 = wave_base(kThreads);
+    // this wave's instance; positions, nodes and leaves below are its own
+    const int64_t g0 = wave_base(kThreads);
+    const Inst &I = inst_of_tile(inst, tile_inst, g0 / kTile);
+    const int64_t n = I.n;
+    const int height = I.height;
+    const int64_t q0 = g0 - I.P;
     const int64_t q = q0 + lane;
     if (q0 >= n)
         return;  // the whole wave lies past the end
+    const C *coords = G.coords + I.P * D;
+    const C *box = G.box + I.N * 2 * D;
+    const uint32_t *rbox = G.rbox + I.N * 2 * D;
+    int32_t *srho = G.srho + I.P;
+    const int32_t *sidx = G.sidx + I.P;
+    int32_t *rho_out = I.rho;
+    // every squared distance is below 2^53 on the double path, so a larger
+    // threshold acts like 2^53
+    const C T = kPacked ? (C)(I.T >= (1ll << 53) ? (1ll << 53) : I.T) : (C)I.T;
+    const C r = (C)I.r;
+    Narrow nw;
+    nw.org = G.org + I.L * D;
+    nw.ext = G.ext + I.L;
+    nw.pack = G.pack + I.P * W;
+#pragma unroll
+    for (int k = 0; k < kMaxDim; ++k)
+        nw.lo[k] = I.lo[k];
+    nw.M = I.M;
+    nw.R = I.R;
+    nw.limit = I.limit;
+    nw.T = I.Tn;
     const bool valid = q < n;
     const int64_t qq = valid ? q : q0;
     C x[D];
@@ -366,17 +403,15 @@ __global__ __launch_bounds__(kThreads) void k_density(const C *__restrict__ coor
 }
 
 template <typename C, bool STATS, bool INTBOX>
-dpc_status launch_typed(const Index &ix, C T, C r, const Narrow &nw, int32_t *srho, int32_t *rho_out,
-                        int64_t *counters, hipStream_t s) {
-    const C *coords = static_cast<const C *>(ix.coords);
-    const C *box = static_cast<const C *>(ix.box);
-    const dim3 grid(blocks_for(ix.n, kThreads)), block(kThreads);
+dpc_status launch_typed(const Index &ix, int32_t *srho, int64_t *counters, hipStream_t s) {
+    DensityArrays<C> G{static_cast<const C *>(ix.coords), static_cast<const C *>(ix.box), ix.rbox, ix.leaf_org,
+                       ix.leaf_ext, ix.leaf_pack, srho, ix.sidx};
+    const dim3 grid(blocks_for(ix.positions, kThreads)), block(kThreads);
     switch (ix.d) {
 #define DPC_DENSITY_CASE(DD)                                                                                    \
     case DD:                                                                                                    \
-        hipLaunchKernelGGL((k_density<C, DD, STATS, INTBOX && DD <= 4>), grid, block, 0, s, coords, box, ix.rbox,  \
-                           ix.n, ix.height, T,                                                                  \
-                           r, nw, srho, ix.sidx, rho_out, counters);                                            \
+        hipLaunchKernelGGL((k_density<C, DD, STATS, INTBOX && DD <= 4>), grid, block, 0, s, ix.inst, ix.tile_inst, \
+                           G, counters);                                                                        \
         break;
         DPC_DENSITY_CASE(1)
         DPC_DENSITY_CASE(2)
@@ -394,46 +429,19 @@ dpc_status launch_typed(const Index &ix, C T, C r, const Narrow &nw, int32_t *sr
     return DPC_OK;
 }
 
-// floor(sqrt(v)) for v >= 0
-int64_t isqrt(int64_t v) {
-    int64_t r = (int64_t)__builtin_sqrt((double)v);
-    while (r > 0 && (__int128)r * r > v)
-        --r;
-    while ((__int128)(r + 1) * (r + 1) <= v)
-        ++r;
-    return r;
-}
-
 }  // namespace
 
-dpc_status launch_density(const Index &ix, int64_t T, int32_t *srho, int32_t *rho_out, int64_t *counters,
-                          hipStream_t s) {
-    const int64_t r = isqrt(T);
-    Narrow nw{};
-    nw.org = ix.leaf_org;
-    nw.ext = ix.leaf_ext;
-    nw.pack = ix.leaf_pack;
-    for (int k = 0; k < kMaxDim; ++k)
-        nw.lo[k] = ix.lo[k];
-    const int64_t R = isqrt((int64_t)INT32_MAX / ix.d) < 32767 ? isqrt((int64_t)INT32_MAX / ix.d) : 32767;
-    const int64_t M = r + 1;
-    nw.R = (int32_t)R;
-    nw.M = (int32_t)(M <= R ? M : R + 1);
-    nw.limit = M <= R ? (int32_t)(R - M) : -1;
-    nw.T = M <= R ? (int32_t)T : 0;
+dpc_status launch_density(const Index &ix, int32_t *srho, int64_t *counters, hipStream_t s) {
     if (ix.arith == Arith::F64) {
-        // every squared distance is below 2^53, so a larger threshold acts like 2^53
-        const double t = T >= (1ll << 53) ? 9007199254740992.0 : (double)T;
-        const double rr = (double)r;
-        // integer boxes when every clamped gap fits (then T < M^2 <= R^2)
-        if (nw.limit >= 0)
-            return counters ? launch_typed<double, true, true>(ix, t, rr, nw, srho, rho_out, counters, s)
-                            : launch_typed<double, false, true>(ix, t, rr, nw, srho, rho_out, nullptr, s);
-        return counters ? launch_typed<double, true, false>(ix, t, rr, nw, srho, rho_out, counters, s)
-                        : launch_typed<double, false, false>(ix, t, rr, nw, srho, rho_out, nullptr, s);
+        // integer boxes when every instance's clamped gaps fit (then T < M^2 <= R^2)
+        if (ix.intbox)
+            return counters ? launch_typed<double, true, true>(ix, srho, counters, s)
+                            : launch_typed<double, false, true>(ix, srho, nullptr, s);
+        return counters ? launch_typed<double, true, false>(ix, srho, counters, s)
+                        : launch_typed<double, false, false>(ix, srho, nullptr, s);
     }
-    return counters ? launch_typed<int64_t, true, false>(ix, T, r, nw, srho, rho_out, counters, s)
-                    : launch_typed<int64_t, false, false>(ix, T, r, nw, srho, rho_out, nullptr, s);
+    return counters ? launch_typed<int64_t, true, false>(ix, srho, counters, s)
+                    : launch_typed<int64_t, false, false>(ix, srho, nullptr, s);
 }
 
 }  // namespace dpc

@@ -44,17 +44,40 @@ __device__ inline void consider(const C (&x)[D], const C (&q)[D], uint64_t kj, u
     best_low = better ? low : best_low;
 }
 
-template <typename C, int D, bool STATS>
+// GROUP = false: one instance, whose arrays and parameters are the kernel's
+// arguments.  GROUP = true: each wave finds its instance from its tile; the
+// arguments are the group's arrays and the rest is read from the
+// instance's descriptor.  (Separate instantiations, so that the single
+// instance keeps every parameter in kernel arguments.)
+template <typename C, int D, bool STATS, bool GROUP>
 __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ coords, const C *__restrict__ box,
                                                         const uint64_t *__restrict__ skey,
                                                         const uint64_t *__restrict__ maxkey,
                                                         const uint64_t *__restrict__ split, Lo lo, int64_t n,
                                                         int height, int32_t rho_min, const int32_t *__restrict__ sidx,
                                                         int32_t *__restrict__ dep_out,
-                                                        int64_t *__restrict__ delta2_out, int64_t *counters) {
+                                                        int64_t *__restrict__ delta2_out, int64_t *counters,
+                                                        const Inst *__restrict__ inst,
+                                                        const uint32_t *__restrict__ tile_inst) {
     uint64_t n_pairs = 0, n_nodes = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
-    const int64_t q0 = wave_base(kThreads);
+    int64_t q0 = wave_base(kThreads);
+    if (GROUP) {
+        const Inst &I = inst_of_tile(inst, tile_inst, q0 / kTile);
+        q0 -= I.P;
+        n = I.n;
+        height = I.height;
+        rho_min = I.dep_rho_min;
+        coords += I.P * D;
+        box += I.N * 2 * D;
+        skey += I.P;
+        maxkey += I.N;
+        split += I.N;
+        sidx += I.P;
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            lo.v[k] = I.lo[k];
+    }
     const int64_t q = q0 + lane;
     if (q0 >= n)
         return;
@@ -175,6 +198,13 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
         --da;
     }
     if (valid) {
+        if (GROUP) {
+            // the output arrays are looked up only now, so that their
+            // addresses do not hold scalar registers during the walk
+            const Inst &J = inst_of_tile(inst, tile_inst, wave_base(kThreads) / kTile);
+            dep_out = J.dep;
+            delta2_out = J.delta2;
+        }
         const int32_t o = sidx[q];
         dep_out[o] = best_low != 0 ? (int32_t)(0xFFFFFFFFu - best_low) : -1;
         delta2_out[o] = best_low != 0 ? (int64_t)best : std::numeric_limits<int64_t>::max();
@@ -187,20 +217,22 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
     }
 }
 
-template <typename C, bool STATS>
-dpc_status launch_typed(const Index &ix, int32_t rho_min, int32_t *dep, int64_t *delta2, int64_t *counters,
-                        hipStream_t s) {
+template <typename C, bool STATS, bool GROUP>
+dpc_status launch_typed(const Index &ix, int64_t *counters, hipStream_t s) {
     const C *coords = static_cast<const C *>(ix.coords);
     const C *box = static_cast<const C *>(ix.box);
-    const dim3 grid(blocks_for(ix.n, kThreads)), block(kThreads);
+    const dim3 grid(blocks_for(ix.positions, kThreads)), block(kThreads);
+    // a single instance's parameters (ignored by the group kernel)
+    const Inst &I = ix.host[0];
     Lo lo{};
     for (int k = 0; k < kMaxDim; ++k)
-        lo.v[k] = ix.lo[k];
+        lo.v[k] = I.lo[k];
     switch (ix.d) {
-#define DPC_DEP_CASE(DD)                                                                                        \
-    case DD:                                                                                                    \
-        hipLaunchKernelGGL((k_dependent<C, DD, STATS>), grid, block, 0, s, coords, box, ix.skey, ix.maxkey,        \
-                           ix.split, lo, ix.n, ix.height, rho_min, ix.sidx, dep, delta2, counters);   \
+#define DPC_DEP_CASE(DD)                                                                                          \
+    case DD:                                                                                                      \
+        hipLaunchKernelGGL((k_dependent<C, DD, STATS, GROUP>), grid, block, 0, s, coords, box, ix.skey, ix.maxkey, \
+                           ix.split, lo, I.n, I.height, I.dep_rho_min, ix.sidx, I.dep, I.delta2, counters, ix.inst, \
+                           ix.tile_inst);                                                                          \
         break;
         DPC_DEP_CASE(1)
         DPC_DEP_CASE(2)
@@ -218,15 +250,17 @@ dpc_status launch_typed(const Index &ix, int32_t rho_min, int32_t *dep, int64_t 
     return DPC_OK;
 }
 
+template <typename C, bool STATS>
+dpc_status launch_arith(const Index &ix, int64_t *counters, hipStream_t s) {
+    return ix.count == 1 ? launch_typed<C, STATS, false>(ix, counters, s) : launch_typed<C, STATS, true>(ix, counters, s);
+}
+
 }  // namespace
 
-dpc_status launch_dependent(const Index &ix, int32_t rho_min, int32_t *dep, int64_t *delta2, int64_t *counters,
-                            hipStream_t s) {
+dpc_status launch_dependent(const Index &ix, int64_t *counters, hipStream_t s) {
     if (ix.arith == Arith::F64)
-        return counters ? launch_typed<double, true>(ix, rho_min, dep, delta2, counters, s)
-                        : launch_typed<double, false>(ix, rho_min, dep, delta2, nullptr, s);
-    return counters ? launch_typed<int64_t, true>(ix, rho_min, dep, delta2, counters, s)
-                    : launch_typed<int64_t, false>(ix, rho_min, dep, delta2, nullptr, s);
+        return counters ? launch_arith<double, true>(ix, counters, s) : launch_arith<double, false>(ix, nullptr, s);
+    return counters ? launch_arith<int64_t, true>(ix, counters, s) : launch_arith<int64_t, false>(ix, nullptr, s);
 }
 
 }  // namespace dpc

@@ -8,10 +8,21 @@
 // box.  Nodes store their tight bounding box and the highest priority key
 // below them: the boxes give the containment count of Section 6.1 and the
 // pruning of Section 3.2, the keys the priority pruning of Section 4.2.2.
+//
+// Every kernel works on a group of instances (independent clustering
+// problems) that share the dimension and the arithmetic: a single call is a
+// group of one.  The instances' arrays are concatenated; instance i's points
+// occupy positions [P_i, P_i + n_i) of the group's point arrays with P_i a
+// multiple of kTile, so that every tile of kTile positions, and every
+// workgroup or wavefront of consecutive positions, belongs to one instance.
+// Positions are instance-local inside the kernels (array pointers are offset
+// by P_i), and so are node and leaf numbers.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <vector>
 
 #include "../../include/libdpc.h"
 
@@ -20,33 +31,90 @@ namespace dpc {
 constexpr int kWave = 64;
 constexpr int kMaxDim = 8;
 constexpr int kLeafSize = 32;  // points per tree leaf
+constexpr int kTile = 2048;    // positions per tile (the unit of the top-level build passes)
 
 // Coordinates and squared distances are exact in double when every squared
 // distance stays below 2^53 (the "f64" path); otherwise 64-bit integers.
 enum class Arith { F64, I64 };
 
-struct Index {
+// One instance as the kernels see it (device memory).
+struct Inst {
+    int64_t n;         // points
+    int64_t P;         // first position in the group's point arrays (a multiple of kTile)
+    int64_t N;         // first node in the group's node arrays (2 * n_leaves nodes)
+    int64_t L;         // first leaf in the group's leaf arrays (n_leaves leaves)
+    int64_t H;         // first word of the instance's top-level histograms
+    int64_t S;         // first entry of its per-node select records (2^(jb-1))
+    int64_t B;         // first word of its top-level relative boxes (2^(jb+1) nodes)
+    int32_t height;    // 2^height leaves
+    int32_t jb;        // first level built in LDS (the top levels are 0 .. jb-1)
+    int32_t wbits;     // bits of the widest coordinate span
+    int32_t lo[kMaxDim];
+    uint32_t span[kMaxDim];
+    // density: the threshold, r = floor(sqrt(T)), and the clamped integer
+    // parameters of the narrow-leaf and integer-box comparisons
+    int64_t T;
+    int64_t r;
+    int32_t M, R, limit, Tn;
+    // dependent points and labels
+    int32_t dep_rho_min;  // dependents of points below it are skipped
+    int32_t rho_min;
+    int64_t Td;
+    // caller's arrays (input order)
+    const int32_t *points;
+    int32_t *rho;
+    int32_t *dep;
+    int64_t *delta2;
+    int32_t *label;
+};
+
+// Host view of one instance before planning.
+struct Job {
+    const int32_t *points = nullptr;
     int64_t n = 0;
-    int d = 0;
-    Arith arith = Arith::F64;
+    int64_t T = 0;          // density threshold (unused by dpc_dependent)
+    int32_t dep_rho_min = 0;
+    int32_t rho_min = 0;
+    int64_t Td = 0;
+    int32_t *rho = nullptr;
+    int32_t *dep = nullptr;
+    int64_t *delta2 = nullptr;
+    int32_t *label = nullptr;
+    // set by the bounds pass
     int32_t lo[kMaxDim] = {0};
     int32_t hi[kMaxDim] = {0};
-    int height = 0;         // tree height: 2^height leaves
-    int64_t n_leaves = 0;   // 2^height
-    // device arrays (owned by the workspace)
-    void *coords = nullptr;     // sorted coordinates [n][d], double or int64
-    int32_t *sidx = nullptr;    // original index of each sorted position [n]
-    void *box = nullptr;        // node boxes [2*n_leaves][d][2] (min, max), like coords
-    uint32_t *rbox = nullptr;   // the same boxes relative to lo, as uint32
-    uint64_t *skey = nullptr;   // priority key of each sorted position [n]
-    uint64_t *maxkey = nullptr; // per-node maximum key [2*n_leaves]
-    // Split of each internal node v < n_leaves: axis << 32 | median offset
-    // from lo along that axis (points below go left).  Only a hint for the
-    // order in which children are searched.
+};
+
+// A group of instances and its device arrays (owned by a Workspace).
+struct Index {
+    int d = 0;
+    Arith arith = Arith::F64;
+    bool intbox = false;        // every instance can use the clamped integer comparisons
+    int count = 0;              // instances
+    std::vector<Inst> host;     // descriptors (host copy)
+    Inst *inst = nullptr;       // descriptors (device)
+    // Instance of each tile (nullptr when the group has one instance).
+    uint32_t *tile_inst = nullptr;
+    int64_t positions = 0;      // padded positions of all instances (a multiple of kTile)
+    int64_t nodes = 0;          // node slots of all instances
+    int64_t leaves = 0;         // leaf slots of all instances
+    int max_height = 0;
+    int max_jb = 0;
+    int max_wbits = 0;
+    // device arrays (owned by the workspace), indexed by position, node or leaf
+    void *coords = nullptr;     // sorted coordinates [pos][d], double or int64
+    int32_t *sidx = nullptr;    // instance-local original index of each sorted position
+    void *box = nullptr;        // node boxes [node][d][2] (min, max), like coords
+    uint32_t *rbox = nullptr;   // the same boxes relative to the instance's lo, as uint32
+    uint64_t *skey = nullptr;   // priority key of each sorted position
+    uint64_t *maxkey = nullptr; // per-node maximum key
+    // Split of each internal node: axis << 32 | median offset from lo along
+    // that axis (points below go left).  Only a hint for the order in which
+    // children are searched.
     uint64_t *split = nullptr;
-    // Leaf records: the leaf box's lower corner relative to lo [n_leaves][d],
-    // its widest side [n_leaves], and every point's offsets from that corner
-    // as 16-bit halves, two axes per word [n][(d+1)/2] (meaningful only when
+    // Leaf records: the leaf box's lower corner relative to lo [leaf][d], its
+    // widest side [leaf], and every point's offsets from that corner as
+    // 16-bit halves, two axes per word [pos][(d+1)/2] (meaningful only when
     // the widest side is below 2^16).
     uint32_t *leaf_org = nullptr;
     uint32_t *leaf_ext = nullptr;
@@ -62,7 +130,7 @@ hipMemPool_t workspace_pool();
 // Stream-ordered device workspace: every allocation is released together.
 struct Workspace {
     hipStream_t stream;
-    static constexpr int kCap = 128;
+    static constexpr int kCap = 160;
     void *ptrs[kCap];
     int count = 0;
     hipMemPool_t pool;
@@ -123,29 +191,61 @@ enum Counter {
     kCounters
 };
 
+// A caller's array named in a descriptor, as a global-memory pointer (the
+// compiler cannot tell the address space of a pointer loaded from memory,
+// and would otherwise emit flat accesses).
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T *global_ptr(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
+// The instance that owns a tile, and the instance-local position of the
+// tile's first element.
+__device__ inline const Inst &inst_of_tile(const Inst *__restrict__ inst, const uint32_t *__restrict__ tile_inst,
+                                           int64_t tile) {
+    return inst[tile_inst ? tile_inst[tile] : 0u];
+}
+
 // Exact thresholds (host).
 dpc_status square_threshold(double r, bool round_up, int64_t *out);
 
+// floor(sqrt(v)) for v >= 0 (host)
+int64_t isqrt64(int64_t v);
+
 // index.hip
-dpc_status build_index(const int32_t *points, int64_t n, int d, int64_t T, Workspace &ws, Index &ix);
-dpc_status build_priority(const int32_t *rho_sorted_or_null, const int32_t *rho_orig_or_null,
-                          Workspace &ws, Index &ix);
+// Bounds of every job (one read-back for all), then the range check and
+// the arithmetic of each.  Fails with DPC_ERR_RANGE if one is out of range
+// (bad[] then marks which, if given).
+dpc_status job_bounds(std::vector<Job> &jobs, int d, Workspace &ws, std::vector<int> *bad);
+Arith job_arith(const Job &j, int d);
+// Plans a group (descriptors, offsets, tile table), allocates its arrays and
+// builds every instance's tree.
+dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, Workspace &ws, Index &ix);
+// Priority keys and per-node maxima; rho in sorted order (srho) or in each
+// instance's input order (rho_orig: use the instances' rho arrays).
+dpc_status build_priority(const int32_t *srho, bool rho_orig, Workspace &ws, Index &ix);
 
-// kdtree.hip: the balanced k-d tree over ix.n points (ix.lo/hi/height/arith
-// set); fills ix.coords, ix.sidx and ix.box.
-dpc_status build_kdtree(const int32_t *points, Workspace &ws, Index &ix);
+// Allocates the group's descriptors (and tile table) and copies them to the
+// device (synchronising the stream).
+dpc_status upload_group(Workspace &ws, Index &ix);
 
-// density.hip; counters (or nullptr) selects the instrumented kernel
-dpc_status launch_density(const Index &ix, int64_t T, int32_t *srho, int32_t *rho_out, int64_t *counters,
-                          hipStream_t s);
+// kdtree.hip: the balanced k-d trees of the group's instances (descriptors
+// planned); allocates the group's arrays, uploads the descriptors and fills
+// coords, sidx, box, rbox, split and the leaf records.
+dpc_status build_kdtree(Workspace &ws, Index &ix);
 
-// dependent.hip; points whose density is below rho_min are skipped
-dpc_status launch_dependent(const Index &ix, int32_t rho_min, int32_t *dep, int64_t *delta2, int64_t *counters,
-                            hipStream_t s);
+// density.hip; srho: sorted-order densities (position-indexed); counters (or
+// nullptr) selects the instrumented kernel
+dpc_status launch_density(const Index &ix, int32_t *srho, int64_t *counters, hipStream_t s);
 
-// cluster.hip
+// dependent.hip
+dpc_status launch_dependent(const Index &ix, int64_t *counters, hipStream_t s);
+
+// cluster.hip: labels of a single instance from arrays in input order
 dpc_status launch_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2,
                           int32_t rho_min, int64_t Td, bool validate, int32_t *label, Workspace &ws);
+// labels of every instance of a group (the edges come from its own outputs)
+dpc_status launch_group_labels(const Index &ix, Workspace &ws);
 
 // Kernel-launch geometry helpers.
 inline unsigned blocks_for(int64_t items, int per_block) {

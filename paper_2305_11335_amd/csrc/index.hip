@@ -1,7 +1,7 @@
-// Spatial index set-up: coordinate bounds (the one host read-back), the
-// choice of exact arithmetic, the tree shape, and after the density step the
-// priority keys and per-node maximum keys.  The k-d tree itself is built in
-// kdtree.hip.
+// Spatial index set-up: coordinate bounds (the host read-back), the choice
+// of exact arithmetic, the layout of a group of instances, the tree shape,
+// and after the density step the priority keys and per-node maximum keys.
+// The k-d trees themselves are built in kdtree.hip.
 #include "dpc_internal.hpp"
 
 #include <limits>
@@ -13,14 +13,6 @@ constexpr int kThreads = 256;
 
 // ---------------------------------------------------------------------------
 // bounds
-
-__global__ void k_bounds_init(int32_t *mm) {
-    const int t = threadIdx.x;
-    if (t < kMaxDim) {
-        mm[t] = std::numeric_limits<int32_t>::max();
-        mm[kMaxDim + t] = std::numeric_limits<int32_t>::min();
-    }
-}
 
 __device__ inline int32_t wave_min(int32_t v) {
 #pragma unroll
@@ -35,6 +27,44 @@ __device__ inline int32_t wave_max(int32_t v) {
     return v;
 }
 
+// Workgroup minimum and maximum per axis of per-thread values (valid in
+// out_min / out_max, shared memory, after the call).
+template <int D>
+__device__ inline void block_bounds(const int32_t (&lmin)[D], const int32_t (&lmax)[D], int32_t *out_min,
+                                    int32_t *out_max) {
+    __shared__ int32_t s_min[kThreads / kWave][D], s_max[kThreads / kWave][D];
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int32_t a = wave_min(lmin[k]), b = wave_max(lmax[k]);
+        if (__lane_id() == 0) {
+            s_min[w][k] = a;
+            s_max[w][k] = b;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < D) {
+        const int k = threadIdx.x;
+        int32_t a = s_min[0][k], b = s_max[0][k];
+        for (int q = 1; q < kThreads / kWave; ++q) {
+            a = min(a, s_min[q][k]);
+            b = max(b, s_max[q][k]);
+        }
+        out_min[k] = a;
+        out_max[k] = b;
+    }
+    __syncthreads();
+}
+
+__global__ void k_bounds_init(int32_t *mm) {
+    const int t = threadIdx.x;
+    if (t < kMaxDim) {
+        mm[t] = std::numeric_limits<int32_t>::max();
+        mm[kMaxDim + t] = std::numeric_limits<int32_t>::min();
+    }
+}
+
+// One instance: a grid-stride pass, combined with atomics.
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_bounds(const int32_t *__restrict__ P, int64_t n, int32_t *mm) {
     int32_t lmin[D], lmax[D];
@@ -52,26 +82,66 @@ __global__ __launch_bounds__(kThreads) void k_bounds(const int32_t *__restrict__
             lmax[k] = max(lmax[k], v);
         }
     }
-    __shared__ int32_t s_min[kThreads / kWave][D], s_max[kThreads / kWave][D];
-    const int w = threadIdx.x / kWave;
+    __shared__ int32_t s_out[2 * D];
+    block_bounds<D>(lmin, lmax, s_out, s_out + D);
+    if (threadIdx.x < D) {
+        atomicMin(&mm[threadIdx.x], s_out[threadIdx.x]);
+        atomicMax(&mm[kMaxDim + threadIdx.x], s_out[D + threadIdx.x]);
+    }
+}
+
+// A group: every workgroup takes one tile of one instance and writes its
+// bounds to the tile's slot; k_bounds_reduce combines each instance's tiles.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_bounds_tiles(const Inst *__restrict__ inst,
+                                                           const uint32_t *__restrict__ tile_inst,
+                                                           int32_t *__restrict__ tmm) {
+    const int64_t tile = blockIdx.x;
+    const Inst &I = inst_of_tile(inst, tile_inst, tile);
+    const int64_t e0 = (tile - I.P / kTile) * kTile;
+    int32_t lmin[D], lmax[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const int32_t a = wave_min(lmin[k]), b = wave_max(lmax[k]);
-        if (__lane_id() == 0) {
-            s_min[w][k] = a;
-            s_max[w][k] = b;
+        lmin[k] = std::numeric_limits<int32_t>::max();
+        lmax[k] = std::numeric_limits<int32_t>::min();
+    }
+    for (int64_t i = e0 + threadIdx.x; i < e0 + kTile && i < I.n; i += kThreads) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int32_t v = I.points[i * D + k];
+            lmin[k] = min(lmin[k], v);
+            lmax[k] = max(lmax[k], v);
         }
     }
-    __syncthreads();
-    if (threadIdx.x < D) {
-        const int k = threadIdx.x;
-        int32_t a = s_min[0][k], b = s_max[0][k];
-        for (int j = 1; j < kThreads / kWave; ++j) {
-            a = min(a, s_min[j][k]);
-            b = max(b, s_max[j][k]);
+    __shared__ int32_t s_out[2 * D];
+    block_bounds<D>(lmin, lmax, s_out, s_out + D);
+    if (threadIdx.x < 2 * D)
+        tmm[tile * 2 * D + threadIdx.x] = s_out[threadIdx.x];
+}
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_bounds_reduce(const Inst *__restrict__ inst,
+                                                            const int32_t *__restrict__ tmm, int32_t *__restrict__ mm) {
+    const Inst &I = inst[blockIdx.x];
+    const int64_t t0 = I.P / kTile, t1 = t0 + (I.n + kTile - 1) / kTile;
+    int32_t lmin[D], lmax[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        lmin[k] = std::numeric_limits<int32_t>::max();
+        lmax[k] = std::numeric_limits<int32_t>::min();
+    }
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += kThreads) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            lmin[k] = min(lmin[k], tmm[t * 2 * D + k]);
+            lmax[k] = max(lmax[k], tmm[t * 2 * D + D + k]);
         }
-        atomicMin(&mm[k], a);
-        atomicMax(&mm[kMaxDim + k], b);
+    }
+    __shared__ int32_t s_out[2 * D];
+    block_bounds<D>(lmin, lmax, s_out, s_out + D);
+    if (threadIdx.x < D) {
+        mm[(int64_t)blockIdx.x * 2 * kMaxDim + threadIdx.x] = s_out[threadIdx.x];
+        mm[(int64_t)blockIdx.x * 2 * kMaxDim + kMaxDim + threadIdx.x] = s_out[D + threadIdx.x];
     }
 }
 
@@ -92,33 +162,41 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int o) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Keys of the sorted positions plus the leaf maxima.  rho comes either in
-// sorted order (srho) or in input order (rho_orig, gathered through sidx).
-__global__ __launch_bounds__(kThreads) void k_keys_leaf(const int32_t *__restrict__ srho,
-                                                        const int32_t *__restrict__ rho_orig,
-                                                        const int32_t *__restrict__ sidx, int64_t n,
-                                                        int64_t n_leaves, uint64_t *__restrict__ skey,
-                                                        uint64_t *__restrict__ maxkey) {
+__global__ void k_fill_u64(uint64_t *__restrict__ a, int64_t m, uint64_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_leaves * kLeafSize)
-        return;
+    if (i < m)
+        a[i] = v;
+}
+
+// Keys of the sorted positions plus the maxima of non-empty leaves (the
+// others stay 0).  rho comes in sorted order (srho, position-indexed) or in
+// each instance's input order (its rho array, through sidx).
+__global__ __launch_bounds__(kThreads) void k_keys_leaf(const Inst *__restrict__ inst,
+                                                        const uint32_t *__restrict__ tile_inst,
+                                                        const int32_t *__restrict__ srho,
+                                                        const int32_t *__restrict__ sidx,
+                                                        uint64_t *__restrict__ skey, uint64_t *__restrict__ maxkey) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Inst &I = inst_of_tile(inst, tile_inst, ((int64_t)blockIdx.x * blockDim.x) / kTile);
+    const int64_t i = pos - I.P;
     uint64_t key = 0;
-    if (i < n) {
-        const int32_t o = sidx[i];
-        const int32_t r = srho ? srho[i] : rho_orig[o];
+    if (i < I.n) {
+        const int32_t o = sidx[pos];
+        const int32_t r = srho ? srho[pos] : I.rho[o];
         key = pack_key(r, o);
-        skey[i] = key;
+        skey[pos] = key;
     }
 #pragma unroll
     for (int o = kLeafSize / 2; o > 0; o >>= 1) {
         const uint64_t b = shfl_xor_u64(key, o);
         key = b > key ? b : key;
     }
-    if ((i & (kLeafSize - 1)) == 0)
-        maxkey[n_leaves + i / kLeafSize] = key;
+    if ((i & (kLeafSize - 1)) == 0 && i < I.n)
+        maxkey[I.N + (1ll << I.height) + i / kLeafSize] = key;
 }
 
-// Up to 8 levels of maxima above 256 consecutive nodes of one depth.
+// One instance: up to 8 levels of maxima above 256 consecutive nodes of one
+// depth.
 __global__ __launch_bounds__(kThreads) void k_key_up(uint64_t *__restrict__ maxkey, int depth_in, int levels) {
     __shared__ uint64_t s[kThreads];
     const int64_t level_base = 1ll << depth_in;
@@ -142,75 +220,259 @@ __global__ __launch_bounds__(kThreads) void k_key_up(uint64_t *__restrict__ maxk
     }
 }
 
-// ---------------------------------------------------------------------------
-// host side
+// A group: the maxima of one depth of every instance (blockIdx.y) from the
+// depth below.
+__global__ __launch_bounds__(kThreads) void k_key_level(const Inst *__restrict__ inst, int depth,
+                                                        uint64_t *__restrict__ maxkey) {
+    const Inst &I = inst[blockIdx.y];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (depth >= I.height || k >= (1ll << depth))
+        return;
+    const int64_t v = (1ll << depth) + k;
+    const uint64_t a = maxkey[I.N + 2 * v], b = maxkey[I.N + 2 * v + 1];
+    maxkey[I.N + v] = a > b ? a : b;
+}
 
-}  // namespace
+int bottom_levels(int d) { return d <= 3 ? 6 : 5; }  // log2 of the LDS subtree size over the leaf size
 
-dpc_status build_index(const int32_t *points, int64_t n, int d, int64_t T, Workspace &ws, Index &ix) {
-    (void)T;
-    hipStream_t s = ws.stream;
-    ix.n = n;
-    ix.d = d;
-    // 1. bounds, read back to the host (the one synchronisation point)
-    int32_t *mm;
-    DPC_TRY(ws.alloc(&mm, 2 * kMaxDim));
-    hipLaunchKernelGGL(k_bounds_init, dim3(1), dim3(kWave), 0, s, mm);
-    const unsigned grid = blocks_for(n, kThreads) < 1024u ? blocks_for(n, kThreads) : 1024u;
-    switch (d) {
-#define DPC_BOUNDS_CASE(DD)                                                                  \
-    case DD:                                                                                 \
-        hipLaunchKernelGGL((k_bounds<DD>), dim3(grid), dim3(kThreads), 0, s, points, n, mm); \
-        break;
-        DPC_BOUNDS_CASE(1)
-        DPC_BOUNDS_CASE(2)
-        DPC_BOUNDS_CASE(3)
-        DPC_BOUNDS_CASE(4)
-        DPC_BOUNDS_CASE(5)
-        DPC_BOUNDS_CASE(6)
-        DPC_BOUNDS_CASE(7)
-        DPC_BOUNDS_CASE(8)
-#undef DPC_BOUNDS_CASE
-    default:
-        return DPC_ERR_INVALID_ARG;
-    }
-    DPC_HIP(hipGetLastError());
-    int32_t host_mm[2 * kMaxDim];
-    DPC_HIP(hipMemcpyAsync(host_mm, mm, sizeof(host_mm), hipMemcpyDeviceToHost, s));
-    DPC_HIP(hipStreamSynchronize(s));
-    unsigned __int128 sum = 0;
-    for (int k = 0; k < d; ++k) {
-        ix.lo[k] = host_mm[k];
-        ix.hi[k] = host_mm[kMaxDim + k];
-        const unsigned __int128 w = (unsigned __int128)((int64_t)ix.hi[k] - (int64_t)ix.lo[k]);
-        sum += w * w;
-    }
-    // 2. every squared distance must fit in int64; below 2^53 doubles are exact
-    if (sum > (unsigned __int128)std::numeric_limits<int64_t>::max())
-        return DPC_ERR_RANGE;
-    ix.arith = sum < ((unsigned __int128)1 << 53) ? Arith::F64 : Arith::I64;
-    // 3. tree shape
+int tree_height(int64_t n) {
     const int64_t leaves = (n + kLeafSize - 1) / kLeafSize;
     int h = 0;
     while ((1ll << h) < leaves)
         ++h;
-    ix.height = h;
-    ix.n_leaves = 1ll << h;
-    return build_kdtree(points, ws, ix);
+    return h;
 }
 
-dpc_status build_priority(const int32_t *srho, const int32_t *rho_orig, Workspace &ws, Index &ix) {
+int64_t padded(int64_t n) { return (n + kTile - 1) / kTile * kTile; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+
+int64_t isqrt64(int64_t v) {
+    int64_t r = (int64_t)__builtin_sqrt((double)v);
+    while (r > 0 && (__int128)r * r > v)
+        --r;
+    while ((__int128)(r + 1) * (r + 1) <= v)
+        ++r;
+    return r;
+}
+
+dpc_status job_bounds(std::vector<Job> &jobs, int d, Workspace &ws, std::vector<int> *bad) {
     hipStream_t s = ws.stream;
-    DPC_TRY(ws.alloc(&ix.skey, ix.n));
-    DPC_TRY(ws.alloc(&ix.maxkey, 2 * ix.n_leaves));
-    hipLaunchKernelGGL(k_keys_leaf, dim3(blocks_for(ix.n_leaves * kLeafSize, kThreads)), dim3(kThreads), 0, s, srho,
-                       rho_orig, ix.sidx, ix.n, ix.n_leaves, ix.skey, ix.maxkey);
-    for (int depth = ix.height; depth > 0;) {
-        const int lv = depth < 8 ? depth : 8;
-        const int64_t nodes = 1ll << depth;
-        const unsigned grid = nodes < kThreads ? 1u : (unsigned)(nodes / kThreads);
-        hipLaunchKernelGGL(k_key_up, dim3(grid), dim3(kThreads), 0, s, ix.maxkey, depth, lv);
-        depth -= lv;
+    const int count = (int)jobs.size();
+    std::vector<int32_t> host_mm((size_t)count * 2 * kMaxDim);
+    if (count == 1) {
+        int32_t *mm;
+        DPC_TRY(ws.alloc(&mm, 2 * kMaxDim));
+        hipLaunchKernelGGL(k_bounds_init, dim3(1), dim3(kWave), 0, s, mm);
+        const unsigned grid = blocks_for(jobs[0].n, kThreads) < 1024u ? blocks_for(jobs[0].n, kThreads) : 1024u;
+        switch (d) {
+#define DPC_BOUNDS_CASE(DD)                                                                                   \
+    case DD:                                                                                                  \
+        hipLaunchKernelGGL((k_bounds<DD>), dim3(grid), dim3(kThreads), 0, s, jobs[0].points, jobs[0].n, mm); \
+        break;
+            DPC_BOUNDS_CASE(1)
+            DPC_BOUNDS_CASE(2)
+            DPC_BOUNDS_CASE(3)
+            DPC_BOUNDS_CASE(4)
+            DPC_BOUNDS_CASE(5)
+            DPC_BOUNDS_CASE(6)
+            DPC_BOUNDS_CASE(7)
+            DPC_BOUNDS_CASE(8)
+#undef DPC_BOUNDS_CASE
+        default:
+            return DPC_ERR_INVALID_ARG;
+        }
+        DPC_HIP(hipGetLastError());
+        DPC_HIP(hipMemcpyAsync(host_mm.data(), mm, 2 * kMaxDim * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    } else {
+        // instances laid out tile by tile, bounds per tile, then per instance
+        std::vector<Inst> pre(count);
+        std::vector<uint32_t> tiles;
+        int64_t P = 0;
+        for (int i = 0; i < count; ++i) {
+            Inst I = {};
+            I.n = jobs[i].n;
+            I.P = P;
+            I.points = jobs[i].points;
+            pre[i] = I;
+            for (int64_t t = 0; t < padded(I.n) / kTile; ++t)
+                tiles.push_back((uint32_t)i);
+            P += padded(I.n);
+        }
+        Inst *d_inst;
+        uint32_t *d_tiles;
+        int32_t *tmm, *mm;
+        DPC_TRY(ws.alloc(&d_inst, (size_t)count));
+        DPC_TRY(ws.alloc(&d_tiles, tiles.size()));
+        DPC_TRY(ws.alloc(&tmm, tiles.size() * 2 * kMaxDim));
+        DPC_TRY(ws.alloc(&mm, (size_t)count * 2 * kMaxDim));
+        DPC_HIP(hipMemcpyAsync(d_inst, pre.data(), count * sizeof(Inst), hipMemcpyHostToDevice, s));
+        DPC_HIP(hipMemcpyAsync(d_tiles, tiles.data(), tiles.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        const unsigned nt = (unsigned)tiles.size();
+        switch (d) {
+#define DPC_BOUNDS_CASE(DD)                                                                                     \
+    case DD:                                                                                                    \
+        hipLaunchKernelGGL((k_bounds_tiles<DD>), dim3(nt), dim3(kThreads), 0, s, d_inst, d_tiles, tmm);          \
+        hipLaunchKernelGGL((k_bounds_reduce<DD>), dim3((unsigned)count), dim3(kThreads), 0, s, d_inst, tmm, mm); \
+        break;
+            DPC_BOUNDS_CASE(1)
+            DPC_BOUNDS_CASE(2)
+            DPC_BOUNDS_CASE(3)
+            DPC_BOUNDS_CASE(4)
+            DPC_BOUNDS_CASE(5)
+            DPC_BOUNDS_CASE(6)
+            DPC_BOUNDS_CASE(7)
+            DPC_BOUNDS_CASE(8)
+#undef DPC_BOUNDS_CASE
+        default:
+            return DPC_ERR_INVALID_ARG;
+        }
+        DPC_HIP(hipGetLastError());
+        DPC_HIP(hipMemcpyAsync(host_mm.data(), mm, host_mm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    DPC_HIP(hipStreamSynchronize(s));
+    dpc_status st = DPC_OK;
+    for (int i = 0; i < count; ++i) {
+        Job &J = jobs[i];
+        unsigned __int128 sum = 0;
+        for (int k = 0; k < d; ++k) {
+            J.lo[k] = host_mm[(size_t)i * 2 * kMaxDim + k];
+            J.hi[k] = host_mm[(size_t)i * 2 * kMaxDim + kMaxDim + k];
+            const unsigned __int128 w = (unsigned __int128)((int64_t)J.hi[k] - (int64_t)J.lo[k]);
+            sum += w * w;
+        }
+        // every squared distance must fit in int64
+        if (sum > (unsigned __int128)std::numeric_limits<int64_t>::max()) {
+            st = DPC_ERR_RANGE;
+            if (bad)
+                bad->push_back(i);
+        }
+    }
+    return st;
+}
+
+Arith job_arith(const Job &J, int d) {
+    unsigned __int128 sum = 0;
+    for (int k = 0; k < d; ++k) {
+        const unsigned __int128 w = (unsigned __int128)((int64_t)J.hi[k] - (int64_t)J.lo[k]);
+        sum += w * w;
+    }
+    // below 2^53 doubles are exact
+    return sum < ((unsigned __int128)1 << 53) ? Arith::F64 : Arith::I64;
+}
+
+dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, Workspace &ws, Index &ix) {
+    hipStream_t s = ws.stream;
+    ix.d = d;
+    ix.arith = arith;
+    ix.count = (int)jobs.size();
+    ix.host.assign(jobs.size(), Inst{});
+    ix.intbox = arith == Arith::F64;
+    int64_t P = 0, N = 0, L = 0, H = 0, S = 0, B = 0;
+    for (int i = 0; i < ix.count; ++i) {
+        const Job &J = jobs[i];
+        Inst &I = ix.host[i];
+        I.n = J.n;
+        I.height = tree_height(J.n);
+        I.jb = I.height > bottom_levels(d) ? I.height - bottom_levels(d) : 0;
+        uint32_t widest = 0;
+        for (int k = 0; k < kMaxDim; ++k) {
+            I.lo[k] = k < d ? J.lo[k] : 0;
+            I.span[k] = k < d ? (uint32_t)((int64_t)J.hi[k] - (int64_t)J.lo[k]) : 0u;
+            widest = I.span[k] > widest ? I.span[k] : widest;
+        }
+        I.wbits = widest ? 32 - __builtin_clz(widest) : 0;
+        I.P = P;
+        I.N = N;
+        I.L = L;
+        I.H = H;
+        I.S = S;
+        I.B = B;
+        P += padded(J.n);
+        N += 2ll << I.height;
+        L += 1ll << I.height;
+        int64_t hw = 0;
+        for (int l = 0; l < I.jb; ++l) {
+            const int bits = l <= 8 ? 11 : 8;  // the digit width of top level l
+            hw += (int64_t)((I.wbits + bits - 1) / bits) * (1ll << l) * (1ll << bits);
+        }
+        H += hw;
+        S += I.jb > 0 ? 1ll << (I.jb - 1) : 0;
+        B += I.jb > 0 ? (2ll << I.jb) * 2 * d : 0;
+        // density thresholds; the clamped integer comparisons need M <= R,
+        // where d * R^2 < 2^31 and R < 2^15
+        I.T = J.T;
+        I.r = isqrt64(J.T);
+        const int64_t R0 = isqrt64((int64_t)std::numeric_limits<int32_t>::max() / d);
+        const int64_t R = R0 < 32767 ? R0 : 32767;
+        const int64_t M = I.r + 1;
+        I.R = (int32_t)R;
+        I.M = (int32_t)(M <= R ? M : R + 1);
+        I.limit = M <= R ? (int32_t)(R - M) : -1;
+        I.Tn = M <= R ? (int32_t)J.T : 0;
+        if (I.limit < 0)
+            ix.intbox = false;
+        I.dep_rho_min = J.dep_rho_min;
+        I.rho_min = J.rho_min;
+        I.Td = J.Td;
+        I.points = J.points;
+        I.rho = J.rho;
+        I.dep = J.dep;
+        I.delta2 = J.delta2;
+        I.label = J.label;
+        ix.max_height = I.height > ix.max_height ? I.height : ix.max_height;
+        ix.max_jb = I.jb > ix.max_jb ? I.jb : ix.max_jb;
+        ix.max_wbits = I.wbits > ix.max_wbits ? I.wbits : ix.max_wbits;
+    }
+    ix.positions = P;
+    ix.nodes = N;
+    ix.leaves = L;
+    (void)s;
+    return build_kdtree(ws, ix);
+}
+
+dpc_status upload_group(Workspace &ws, Index &ix) {
+    hipStream_t s = ws.stream;
+    DPC_TRY(ws.alloc(&ix.inst, (size_t)ix.count));
+    DPC_HIP(hipMemcpyAsync(ix.inst, ix.host.data(), ix.count * sizeof(Inst), hipMemcpyHostToDevice, s));
+    std::vector<uint32_t> tiles;
+    if (ix.count > 1) {
+        for (int i = 0; i < ix.count; ++i)
+            for (int64_t t = 0; t < padded(ix.host[i].n) / kTile; ++t)
+                tiles.push_back((uint32_t)i);
+        DPC_TRY(ws.alloc(&ix.tile_inst, tiles.size()));
+        DPC_HIP(hipMemcpyAsync(ix.tile_inst, tiles.data(), tiles.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    }
+    DPC_HIP(hipStreamSynchronize(s));  // the host copies go out of scope
+    return DPC_OK;
+}
+
+dpc_status build_priority(const int32_t *srho, bool rho_orig, Workspace &ws, Index &ix) {
+    hipStream_t s = ws.stream;
+    (void)rho_orig;  // without srho the keys read each instance's rho array
+    DPC_TRY(ws.alloc(&ix.skey, (size_t)ix.positions));
+    DPC_TRY(ws.alloc(&ix.maxkey, (size_t)ix.nodes));
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(ix.nodes, kThreads)), dim3(kThreads), 0, s, ix.maxkey, ix.nodes,
+                       (uint64_t)0);
+    hipLaunchKernelGGL(k_keys_leaf, dim3(blocks_for(ix.positions, kThreads)), dim3(kThreads), 0, s, ix.inst,
+                       ix.tile_inst, srho, ix.sidx, ix.skey, ix.maxkey);
+    if (ix.count == 1) {
+        for (int depth = ix.host[0].height; depth > 0;) {
+            const int lv = depth < 8 ? depth : 8;
+            const int64_t nodes = 1ll << depth;
+            const unsigned grid = nodes < kThreads ? 1u : (unsigned)(nodes / kThreads);
+            hipLaunchKernelGGL(k_key_up, dim3(grid), dim3(kThreads), 0, s, ix.maxkey, depth, lv);
+            depth -= lv;
+        }
+    } else {
+        for (int depth = ix.max_height - 1; depth >= 0; --depth) {
+            const unsigned gx = blocks_for(1ll << depth, kThreads);
+            hipLaunchKernelGGL(k_key_level, dim3(gx, (unsigned)ix.count), dim3(kThreads), 0, s, ix.inst, depth,
+                               ix.maxkey);
+        }
     }
     DPC_HIP(hipGetLastError());
     return DPC_OK;

@@ -22,7 +22,8 @@
 // arrays.
 //
 // Every 2048-point tile of the top levels lies inside a single node, because
-// node sizes there are multiples of the tile.
+// node sizes there are multiples of the tile, and inside a single instance of
+// the group; each kernel finds its instance from its tile.
 #include "dpc_internal.hpp"
 
 #include <limits>
@@ -32,7 +33,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
-constexpr int kTile = 2048;
 constexpr int kItems = kTile / kThreads;    // 8
 constexpr int kWaveItems = kItems * kWave;  // 512
 
@@ -51,14 +51,6 @@ struct Bottom {
     static constexpr int kLevels = D <= 3 ? 6 : 5;    // log2(kSize / kLeafSize)
     static constexpr int kNodes = kSize / kLeafSize;  // most nodes on one level
     static_assert((kLeafSize << kLevels) == kSize, "subtree size");
-};
-
-struct Origin {
-    int32_t v[kMaxDim];  // global coordinate minimum per axis
-};
-
-struct Spans {
-    uint32_t v[kMaxDim];  // max - min per axis
 };
 
 __device__ inline uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
@@ -158,6 +150,80 @@ __device__ inline NodeGeom node_geom(int64_t t, int64_t S, int64_t n) {
     return g;
 }
 
+// Digit width of a top level: 11 bits while the level has at most 256 nodes
+// (fewer passes), 8 bits below (small histograms for many nodes).
+constexpr int kWideLevels = 8;
+
+__host__ __device__ inline int level_bits(int j) { return j <= kWideLevels ? 11 : 8; }
+
+// Words of an instance's histograms of levels [0, j): passes x nodes x bins.
+__host__ __device__ inline int64_t hist_words_below(int j, int wbits) {
+    int64_t w = 0;
+    for (int l = 0; l < j; ++l) {
+        const int bits = level_bits(l);
+        w += (int64_t)((wbits + bits - 1) / bits) * (1ll << l) * (1ll << bits);
+    }
+    return w;
+}
+
+// A tile of the top-level passes at level j: its instance and the
+// instance-local geometry of the tile and of its node.
+struct TopTile {
+    const Inst *I;
+    int64_t e0;     // instance-local first position
+    int64_t t;      // the node's index within level j
+    int64_t tile0;  // group tile of the node's first position
+    NodeGeom g;
+};
+
+// False when the tile has no work at level j (padding, or an instance whose
+// level j is built in LDS).
+__device__ inline bool top_tile(const Inst *__restrict__ inst, const uint32_t *__restrict__ tile_inst, int64_t tile,
+                                int j, TopTile &tt) {
+    const Inst &I = inst_of_tile(inst, tile_inst, tile);
+    if (j >= I.jb)
+        return false;
+    const int64_t first = I.P / kTile;
+    tt.e0 = (tile - first) * kTile;
+    if (tt.e0 >= I.n)
+        return false;
+    tt.I = &I;
+    const int64_t S = (int64_t)kLeafSize << (I.height - j);
+    tt.t = tt.e0 / S;
+    tt.g = node_geom(tt.t, S, I.n);
+    tt.tile0 = first + tt.g.start / kTile;
+    return true;
+}
+
+// A node of level j, for the kernels with one workgroup per node: from the
+// group's node table, or node blockIdx.x of the single instance.
+__device__ inline bool top_node(const Inst *__restrict__ inst, const uint2 *__restrict__ node_tab, int j,
+                                TopTile &tt) {
+    const uint2 e = node_tab ? node_tab[blockIdx.x] : make_uint2(0u, blockIdx.x);
+    const Inst &I = inst[e.x];
+    if (j >= I.jb)
+        return false;
+    const int64_t S = (int64_t)kLeafSize << (I.height - j);
+    tt.t = e.y;
+    if (tt.t * S >= I.n)
+        return false;
+    tt.I = &I;
+    tt.g = node_geom(tt.t, S, I.n);
+    tt.e0 = tt.g.start;
+    tt.tile0 = I.P / kTile + tt.g.start / kTile;
+    return true;
+}
+
+// Per-instance pieces of the group's top-level work arrays.
+struct TopArrays {
+    uint32_t *X;          // [d][positions] coordinates relative to lo (this pass's input)
+    int64_t positions;
+    uint32_t *nboxes;     // relative node boxes of the top levels
+    uint32_t *hist;
+    void *state;          // SelectState records
+    void *split;          // NodeSplit records
+};
+
 struct NodeSelect {
     int axis;
     uint32_t base;  // the box minimum along the axis; select works on x - base
@@ -218,30 +284,41 @@ __device__ inline void pick_digit(const uint32_t *__restrict__ hp, SelectState &
 // keep the number of global additions to one bin low on the first levels,
 // where every workgroup works on one of very few nodes.
 template <int D, int BITS>
-__global__ __launch_bounds__(kThreads) void k_sel_hist(const uint32_t *__restrict__ X, int64_t n, int j, int h,
-                                                       const uint32_t *__restrict__ boxes, uint32_t *__restrict__ hist,
-                                                       int pass, const SelectState *__restrict__ state, int tiles) {
+__global__ __launch_bounds__(kThreads) void k_sel_hist(const Inst *__restrict__ inst,
+                                                       const uint32_t *__restrict__ tile_inst,
+                                                       const uint32_t *__restrict__ blocks, int per, TopArrays A,
+                                                       int j, int pass) {
     using Dg = Digit<BITS>;
     __shared__ uint32_t s_h[Dg::kBins];
-    const int64_t b0 = (int64_t)blockIdx.x * tiles * kTile;
-    if (b0 >= n)
+    // this workgroup's tiles: from the table (a group), or `per` at a time
+    int64_t tile;
+    int tiles;
+    if (blocks) {
+        tile = blocks[blockIdx.x] >> 4;
+        tiles = (int)(blocks[blockIdx.x] & 15u) + 1;
+    } else {
+        tile = (int64_t)blockIdx.x * per;
+        tiles = per;
+    }
+    TopTile tt;
+    if (!top_tile(inst, tile_inst, tile, j, tt))
         return;
-    const int64_t S = (int64_t)kLeafSize << (h - j);
-    const int64_t t = b0 / S;
-    const NodeGeom g = node_geom(t, S, n);
-    const NodeSelect ns = node_select<D, BITS>(boxes + t * 2 * D);
-    if (pass >= ns.passes || g.half == g.count)
+    const Inst &I = *tt.I;
+    const int64_t n = I.n;
+    const uint32_t *nbox = A.nboxes + I.B + tt.t * 2 * D + (1ll << j) * 2 * D;
+    const NodeSelect ns = node_select<D, BITS>(nbox);
+    if (pass >= ns.passes || tt.g.half == tt.g.count)
         return;  // this node's median is already known (or it has no right half)
-    const int64_t pass_stride = (1ll << j) * Dg::kBins;
-    const SelectState st = pass == 0 ? SelectState{0u, 0u, (uint32_t)g.half} : state[t];
+    const SelectState *state = static_cast<const SelectState *>(A.state) + I.S;
+    const SelectState st = pass == 0 ? SelectState{0u, 0u, (uint32_t)tt.g.half} : state[tt.t];
     const int shift = (ns.passes - 1 - pass) * BITS;
     for (int b = threadIdx.x; b < Dg::kBins; b += kThreads)
         s_h[b] = 0;
     __syncthreads();
-    const uint32_t *x = X + (int64_t)ns.axis * n;
+    const uint32_t *x = A.X + (int64_t)ns.axis * A.positions + I.P;
     const int w = threadIdx.x / kWave;
-    for (int tt = 0; tt < tiles; ++tt) {
-        const int64_t e0 = b0 + (int64_t)tt * kTile;
+    for (int q = 0; q < tiles; ++q) {
+        const int64_t e0 = tt.e0 + (int64_t)q * kTile;
         if (e0 >= n)
             break;
         uint32_t xv[kItems];
@@ -265,7 +342,8 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const uint32_t *__restric
         }
     }
     __syncthreads();
-    uint32_t *hp = hist + (int64_t)pass * pass_stride + t * Dg::kBins;
+    uint32_t *hp = A.hist + I.H + hist_words_below(j, I.wbits) + (int64_t)pass * (1ll << j) * Dg::kBins +
+                   tt.t * Dg::kBins;
     for (int b = threadIdx.x; b < Dg::kBins; b += kThreads) {
         const uint32_t c = s_h[b];
         if (c)
@@ -273,27 +351,29 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const uint32_t *__restric
     }
 }
 
-// Chooses each node's digit of this pass from its finished histogram (one
-// workgroup per node) and stores the node's state for the next pass.
+// Chooses each node's digit of this pass from its finished histogram and
+// stores the node's state for the next pass (one workgroup per node).
 template <int D, int BITS>
-__global__ __launch_bounds__(kThreads) void k_sel_pick(int64_t n, int j, int h, const uint32_t *__restrict__ boxes,
-                                                       const uint32_t *__restrict__ hist, int pass,
-                                                       SelectState *__restrict__ state) {
+__global__ __launch_bounds__(kThreads) void k_sel_pick(const Inst *__restrict__ inst,
+                                                       const uint2 *__restrict__ node_tab, TopArrays A, int j,
+                                                       int pass) {
     using Dg = Digit<BITS>;
     __shared__ uint32_t s_w[kWaves];
     __shared__ uint32_t s_pick[2];
-    const int64_t t = blockIdx.x;
-    const int64_t S = (int64_t)kLeafSize << (h - j);
-    if (t * S >= n)
+    TopTile tt;
+    if (!top_node(inst, node_tab, j, tt))
         return;
-    const NodeGeom g = node_geom(t, S, n);
-    const NodeSelect ns = node_select<D, BITS>(boxes + t * 2 * D);
-    if (pass >= ns.passes || g.half == g.count)
+    const Inst &I = *tt.I;
+    const NodeSelect ns = node_select<D, BITS>(A.nboxes + I.B + ((1ll << j) + tt.t) * 2 * D);
+    if (pass >= ns.passes || tt.g.half == tt.g.count)
         return;
-    SelectState st = pass == 0 ? SelectState{0u, 0u, (uint32_t)g.half} : state[t];
-    pick_digit<BITS>(hist + (int64_t)pass * (1ll << j) * Dg::kBins + t * Dg::kBins, st, s_w, s_pick);
+    SelectState *state = static_cast<SelectState *>(A.state) + I.S;
+    SelectState st = pass == 0 ? SelectState{0u, 0u, (uint32_t)tt.g.half} : state[tt.t];
+    pick_digit<BITS>(A.hist + I.H + hist_words_below(j, I.wbits) + (int64_t)pass * (1ll << j) * Dg::kBins +
+                         tt.t * Dg::kBins,
+                     st, s_w, s_pick);
     if (threadIdx.x == 0)
-        state[t] = st;
+        state[tt.t] = st;
 }
 
 struct NodeSplit {
@@ -304,54 +384,54 @@ struct NodeSplit {
     int32_t all_left;  // the node has no right half
 };
 
+// Per-tile counts of points below and equal to their node's median (the
+// workgroup of a node's first tile also records the node's split and box).
 template <typename C, int D, int BITS>
-__global__ __launch_bounds__(kThreads) void k_part_count(const uint32_t *__restrict__ X, int64_t n, int j, int h,
-                                                         const uint32_t *__restrict__ boxes,
-                                                         const SelectState *__restrict__ state,
-                                                         NodeSplit *__restrict__ split, uint32_t *__restrict__ cnt_less,
-                                                         uint32_t *__restrict__ cnt_eq, C *__restrict__ tree_box,
-                                                         uint32_t *__restrict__ rel_box, uint64_t *__restrict__ split_hint,
-                                                         Origin origin) {
+__global__ __launch_bounds__(kThreads) void k_part_count(const Inst *__restrict__ inst,
+                                                         const uint32_t *__restrict__ tile_inst, TopArrays A, int j,
+                                                         uint32_t *__restrict__ cnt_less, uint32_t *__restrict__ cnt_eq,
+                                                         C *__restrict__ tree_box, uint32_t *__restrict__ rel_box,
+                                                         uint64_t *__restrict__ split_hint) {
     __shared__ uint32_t s_c[2][kWaves];
-    const int64_t e0 = (int64_t)blockIdx.x * kTile;
-    if (e0 >= n)
+    TopTile tt;
+    if (!top_tile(inst, tile_inst, blockIdx.x, j, tt))
         return;
-    const int64_t S = (int64_t)kLeafSize << (h - j);
-    const int64_t t = e0 / S;
-    const NodeGeom g = node_geom(t, S, n);
-    const uint32_t *nb = boxes + t * 2 * D;
+    const Inst &I = *tt.I;
+    const int64_t n = I.n;
+    const NodeGeom g = tt.g;
+    const uint32_t *nb = A.nboxes + I.B + ((1ll << j) + tt.t) * 2 * D;
     const NodeSelect ns = node_select<D, BITS>(nb);
     const bool all_left = g.half == g.count;
-    const SelectState st =
-        (all_left || ns.passes == 0) ? SelectState{0u, 0u, (uint32_t)g.half} : state[t];
+    const SelectState st = (all_left || ns.passes == 0) ? SelectState{0u, 0u, (uint32_t)g.half}
+                                                        : (static_cast<const SelectState *>(A.state) + I.S)[tt.t];
     // with every digit chosen, prefix is the exact median and rank its rank
     // among the points equal to it
-    if (e0 == g.start && threadIdx.x == 0) {
+    if (tt.e0 == g.start && threadIdx.x == 0) {
         NodeSplit sp;
         sp.base = ns.base;
         sp.median = st.prefix;
         sp.need_eq = st.rank;
         sp.axis = ns.axis;
         sp.all_left = all_left ? 1 : 0;
-        split[t] = sp;
-        split_hint[(1ll << j) + t] = ((uint64_t)(uint32_t)sp.axis << 32) | (uint64_t)(sp.base + sp.median);
-        const int64_t v = (1ll << j) + t;
+        (static_cast<NodeSplit *>(A.split) + I.S)[tt.t] = sp;
+        const int64_t v = (1ll << j) + tt.t;
+        split_hint[I.N + v] = ((uint64_t)(uint32_t)sp.axis << 32) | (uint64_t)(sp.base + sp.median);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            tree_box[(v * D + k) * 2 + 0] = (C)((int64_t)origin.v[k] + (int64_t)nb[2 * k]);
-            tree_box[(v * D + k) * 2 + 1] = (C)((int64_t)origin.v[k] + (int64_t)nb[2 * k + 1]);
-            rel_box[(v * D + k) * 2 + 0] = nb[2 * k];
-            rel_box[(v * D + k) * 2 + 1] = nb[2 * k + 1];
+            tree_box[((I.N + v) * D + k) * 2 + 0] = (C)((int64_t)I.lo[k] + (int64_t)nb[2 * k]);
+            tree_box[((I.N + v) * D + k) * 2 + 1] = (C)((int64_t)I.lo[k] + (int64_t)nb[2 * k + 1]);
+            rel_box[((I.N + v) * D + k) * 2 + 0] = nb[2 * k];
+            rel_box[((I.N + v) * D + k) * 2 + 1] = nb[2 * k + 1];
         }
     }
-    const uint32_t *x = X + (int64_t)ns.axis * n;
+    const uint32_t *x = A.X + (int64_t)ns.axis * A.positions + I.P;
     const int w = threadIdx.x / kWave;
     uint32_t xv[kItems];
-    load_items(x, n, e0 + (int64_t)w * kWaveItems, xv);
+    load_items(x, n, tt.e0 + (int64_t)w * kWaveItems, xv);
     uint32_t nl = 0, ne = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const int64_t e = e0 + (int64_t)w * kWaveItems + (int64_t)r * kWave + __lane_id();
+        const int64_t e = tt.e0 + (int64_t)w * kWaveItems + (int64_t)r * kWave + __lane_id();
         const uint32_t v = xv[r] - ns.base;
         const bool less = e < n && (all_left || v < st.prefix);
         const bool eq = e < n && !all_left && v == st.prefix;
@@ -376,7 +456,9 @@ __global__ __launch_bounds__(kThreads) void k_part_count(const uint32_t *__restr
 
 // Exclusive scans of the per-tile counts (block 0: less, block 1: equal):
 // each thread sums a contiguous run of tiles, one block scan, then each
-// thread writes its run's prefixes.
+// thread writes its run's prefixes.  Tiles without work at this level hold
+// stale counts; they cancel, because a tile only ever subtracts the prefix at
+// its own node's first tile.
 constexpr int kScanThreads = 1024;
 
 __global__ __launch_bounds__(kScanThreads) void k_part_scan(uint32_t *__restrict__ cnt_less,
@@ -398,24 +480,29 @@ __global__ __launch_bounds__(kScanThreads) void k_part_scan(uint32_t *__restrict
 }
 
 template <int D>
-__global__ __launch_bounds__(kThreads) void k_part_scatter(const uint32_t *__restrict__ Xin,
-                                                           const uint32_t *__restrict__ Iin,
-                                                           uint32_t *__restrict__ Xout, uint32_t *__restrict__ Iout,
-                                                           int64_t n, int j, int h,
-                                                           const NodeSplit *__restrict__ split,
+__global__ __launch_bounds__(kThreads) void k_part_scatter(const Inst *__restrict__ inst,
+                                                           const uint32_t *__restrict__ tile_inst, TopArrays A,
+                                                           const uint32_t *__restrict__ Iin_all,
+                                                           uint32_t *__restrict__ Xout_all,
+                                                           uint32_t *__restrict__ Iout_all, int j,
                                                            const uint32_t *__restrict__ scan_less,
                                                            const uint32_t *__restrict__ scan_eq,
                                                            uint32_t *__restrict__ tile_box) {
     __shared__ uint32_t s_w[2][kWaves];
     __shared__ uint32_t s_box[2][D][2];
-    const int64_t e0 = (int64_t)blockIdx.x * kTile;
-    if (e0 >= n)
+    TopTile tt;
+    if (!top_tile(inst, tile_inst, blockIdx.x, j, tt))
         return;
-    const int64_t S = (int64_t)kLeafSize << (h - j);
-    const int64_t t = e0 / S;
-    const NodeGeom g = node_geom(t, S, n);
-    const NodeSplit sp = split[t];
-    const int64_t tile0 = g.start / kTile;
+    const Inst &I = *tt.I;
+    const int64_t n = I.n, e0 = tt.e0, tile0 = tt.tile0;
+    const NodeGeom g = tt.g;
+    const NodeSplit sp = (static_cast<const NodeSplit *>(A.split) + I.S)[tt.t];
+    // instance-local views of the group arrays
+    const int64_t np = A.positions;
+    const uint32_t *Xin = A.X + I.P;
+    const uint32_t *Iin = Iin_all + I.P;
+    uint32_t *Xout = Xout_all + I.P;
+    uint32_t *Iout = Iout_all + I.P;
     // points of this node before this tile that are below / equal to the median
     const uint32_t less_base = scan_less[blockIdx.x] - scan_less[tile0];
     const uint32_t eq_base = scan_eq[blockIdx.x] - scan_eq[tile0];
@@ -430,7 +517,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(const uint32_t *__res
     uint32_t xv[D][kItems], iv[kItems];
 #pragma unroll
     for (int k = 0; k < D; ++k)
-        load_items(Xin + (int64_t)k * n, n, ew, xv[k]);
+        load_items(Xin + (int64_t)k * np, n, ew, xv[k]);
     load_items(Iin, n, ew, iv);
     uint32_t lb[kItems], eb[kItems];
     uint32_t less_bits = 0, eq_bits = 0;
@@ -486,7 +573,7 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(const uint32_t *__res
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const uint32_t v = xv[k][r];
-            Xout[(int64_t)k * n + dst] = v;
+            Xout[(int64_t)k * np + dst] = v;
             if (left) {
                 lmin[k] = v < lmin[k] ? v : lmin[k];
                 lmax[k] = v > lmax[k] ? v : lmax[k];
@@ -522,16 +609,18 @@ __global__ __launch_bounds__(kThreads) void k_part_scatter(const uint32_t *__res
 // The children's boxes of every node of level j from the per-tile shares
 // (one workgroup per node).
 template <int D>
-__global__ __launch_bounds__(kThreads) void k_box_reduce(int64_t n, int j, int h,
-                                                         const uint32_t *__restrict__ tile_box,
-                                                         uint32_t *__restrict__ child_boxes) {
+__global__ __launch_bounds__(kThreads) void k_box_reduce(const Inst *__restrict__ inst,
+                                                         const uint2 *__restrict__ node_tab, TopArrays A, int j,
+                                                         const uint32_t *__restrict__ tile_box) {
     __shared__ uint32_t s_r[kWaves][4 * D];
-    const int64_t t = blockIdx.x;
-    const int64_t S = (int64_t)kLeafSize << (h - j);
-    if (t * S >= n)
+    TopTile tt;
+    if (!top_node(inst, node_tab, j, tt))
         return;
-    const NodeGeom g = node_geom(t, S, n);
-    const int64_t t0 = g.start / kTile, t1 = (g.start + g.count + kTile - 1) / kTile;
+    const Inst &I = *tt.I;
+    const int64_t t = tt.t;
+    const NodeGeom g = tt.g;
+    uint32_t *child_boxes = A.nboxes + I.B + (2ll << j) * 2 * D;
+    const int64_t t0 = tt.tile0, t1 = tt.tile0 + (g.count + kTile - 1) / kTile;
     uint32_t acc[4 * D];
 #pragma unroll
     for (int i = 0; i < 4 * D; ++i)
@@ -568,39 +657,56 @@ __global__ void k_fill_u32(uint32_t *__restrict__ a, int64_t m, uint32_t v) {
         a[i] = v;
 }
 
-// the root's box in relative coordinates: [0, span] on every axis
+// each instance's root box in relative coordinates: [0, span] on every axis
+// (instances built entirely in LDS have none)
 template <int D>
-__global__ void k_root_box(uint32_t *__restrict__ nb, Spans spans) {
-    const int k = threadIdx.x;
-    if (k < D) {
+__global__ void k_root_box(const Inst *__restrict__ inst, int count, uint32_t *__restrict__ nboxes) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count)
+        return;
+    const Inst &I = inst[i];
+    if (I.jb == 0)
+        return;
+    uint32_t *nb = nboxes + I.B + 2 * D;  // node 1
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
         nb[2 * k] = 0u;
-        nb[2 * k + 1] = spans.v[k];
+        nb[2 * k + 1] = I.span[k];
     }
 }
 
+// Coordinates relative to lo in structure-of-arrays form, and the identity
+// permutation, at every instance's positions.
 template <int D>
-__global__ __launch_bounds__(kThreads) void k_soa_init(const int32_t *__restrict__ P, int64_t n, Origin origin,
-                                                       uint32_t *__restrict__ X, uint32_t *__restrict__ I) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
+__global__ __launch_bounds__(kThreads) void k_soa_init(const Inst *__restrict__ inst,
+                                                       const uint32_t *__restrict__ tile_inst, int64_t positions,
+                                                       uint32_t *__restrict__ X, uint32_t *__restrict__ Ids) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Inst &I = inst_of_tile(inst, tile_inst, ((int64_t)blockIdx.x * blockDim.x) / kTile);
+    const int64_t i = pos - I.P;
+    if (i >= I.n)
         return;
+    const int32_t *P = I.points;
 #pragma unroll
     for (int k = 0; k < D; ++k)
-        X[(int64_t)k * n + i] = (uint32_t)((int64_t)P[i * D + k] - (int64_t)origin.v[k]);
-    I[i] = (uint32_t)i;
+        X[(int64_t)k * positions + pos] = (uint32_t)((int64_t)P[i * D + k] - (int64_t)I.lo[k]);
+    Ids[pos] = (uint32_t)i;
 }
 
 // ---------------------------------------------------------------------------
 // bottom levels: one workgroup per subtree, in LDS
 
 template <typename C, int D>
-__global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict__ X, const uint32_t *__restrict__ I,
-                                                     int64_t n, int jb, int h, Origin origin, C *__restrict__ tree_box,
-                                                     uint32_t *__restrict__ rel_box,
-                                                     C *__restrict__ coords, int32_t *__restrict__ sidx,
-                                                     uint32_t *__restrict__ leaf_org, uint32_t *__restrict__ leaf_ext,
-                                                     uint32_t *__restrict__ leaf_pack,
-                                                     uint64_t *__restrict__ split_hint) {
+__global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ inst, const uint2 *__restrict__ sub,
+                                                     const uint32_t *__restrict__ XA, const uint32_t *__restrict__ XB,
+                                                     const uint32_t *__restrict__ IA, const uint32_t *__restrict__ IB,
+                                                     int64_t np,
+                                                     C *__restrict__ tree_box_all, uint32_t *__restrict__ rel_box_all,
+                                                     C *__restrict__ coords_all, int32_t *__restrict__ sidx_all,
+                                                     uint32_t *__restrict__ leaf_org_all,
+                                                     uint32_t *__restrict__ leaf_ext_all,
+                                                     uint32_t *__restrict__ leaf_pack_all,
+                                                     uint64_t *__restrict__ split_hint_all) {
     constexpr int M = Bottom<D>::kSize;
     constexpr int NB = Bottom<D>::kNodes;
     constexpr int PER = M / kThreads;
@@ -615,16 +721,34 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
     __shared__ uint32_t s_pick[kWaves][2];
     __shared__ uint32_t s_cnt[kWaves][2];
 
+    // this workgroup's instance and subtree (a group of one: blockIdx)
+    const uint2 job = sub ? sub[blockIdx.x] : make_uint2(0u, blockIdx.x);
+    const Inst &In = inst[job.x];
+    const int64_t n = In.n;
+    const int jb = In.jb, h = In.height;
+    constexpr int W = (D + 1) / 2;
+    // after jb top-level passes (each moves the points to the other buffer)
+    // the instance's points are in buffer jb mod 2
+    const uint32_t *X = ((jb & 1) ? XB : XA) + In.P;
+    const uint32_t *ids = ((jb & 1) ? IB : IA) + In.P;
+    C *tree_box = tree_box_all + In.N * 2 * D;
+    uint32_t *rel_box = rel_box_all + In.N * 2 * D;
+    C *coords = coords_all + In.P * D;
+    int32_t *sidx = sidx_all + In.P;
+    uint32_t *leaf_org = leaf_org_all + In.L * D;
+    uint32_t *leaf_ext = leaf_ext_all + In.L;
+    uint32_t *leaf_pack = leaf_pack_all + In.P * W;
+    uint64_t *split_hint = split_hint_all + In.N;
     const int64_t S0 = (int64_t)kLeafSize << (h - jb);  // at most M
-    const int64_t s0 = (int64_t)blockIdx.x * S0;
+    const int64_t s0 = (int64_t)job.y * S0;
     if (s0 >= n)
         return;
     const int cnt0 = (int)(n - s0 < S0 ? n - s0 : S0);
     for (int i = threadIdx.x; i < cnt0; i += kThreads) {
 #pragma unroll
         for (int k = 0; k < D; ++k)
-            s_x[k][i] = X[(int64_t)k * n + s0 + i];
-        s_id[i] = I[s0 + i];
+            s_x[k][i] = X[(int64_t)k * np + s0 + i];
+        s_id[i] = ids[s0 + i];
     }
     const int w = threadIdx.x / kWave;
     const int lane = __lane_id();
@@ -664,8 +788,8 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
             uint32_t ext = 0;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                tree_box[(v * D + k) * 2 + 0] = (C)((int64_t)origin.v[k] + (int64_t)s_box[u][k][0]);
-                tree_box[(v * D + k) * 2 + 1] = (C)((int64_t)origin.v[k] + (int64_t)s_box[u][k][1]);
+                tree_box[(v * D + k) * 2 + 0] = (C)((int64_t)In.lo[k] + (int64_t)s_box[u][k][0]);
+                tree_box[(v * D + k) * 2 + 1] = (C)((int64_t)In.lo[k] + (int64_t)s_box[u][k][1]);
                 rel_box[(v * D + k) * 2 + 0] = s_box[u][k][0];
                 rel_box[(v * D + k) * 2 + 1] = s_box[u][k][1];
                 const uint32_t e = s_box[u][k][1] - s_box[u][k][0];
@@ -913,11 +1037,10 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
         __syncthreads();
     }
     __syncthreads();
-    constexpr int W = (D + 1) / 2;
     for (int i = threadIdx.x; i < cnt0; i += kThreads) {
 #pragma unroll
         for (int k = 0; k < D; ++k)
-            coords[(s0 + i) * D + k] = (C)((int64_t)origin.v[k] + (int64_t)s_x[k][i]);
+            coords[(s0 + i) * D + k] = (C)((int64_t)In.lo[k] + (int64_t)s_x[k][i]);
         sidx[s0 + i] = (int32_t)s_id[i];
         // offsets from the leaf corner, two 16-bit halves per word (read only
         // for leaves narrow enough that every offset fits)
@@ -931,134 +1054,184 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const uint32_t *__restrict_
     }
 }
 
-// Digit width of a top level: 11 bits while the level has at most 256 nodes
-// (fewer passes), 8 bits below (small histograms for many nodes).
-constexpr int kWideLevels = 8;
-
-inline int level_bits(int j) { return j <= kWideLevels ? 11 : 8; }
-
-template <typename C, int D, int BITS>
-void launch_level(const uint32_t *Xin, const uint32_t *Iin, uint32_t *Xout, uint32_t *Iout, int64_t n, int j, int h,
-                  int passes, const uint32_t *bj, uint32_t *bj1, uint32_t *hj, SelectState *state,
-                  NodeSplit *split, uint32_t *cnt_less, uint32_t *cnt_eq, uint32_t *tile_box, C *box,
-                  uint32_t *rel_box, uint64_t *split_hint, Origin origin,
-                  unsigned grid, unsigned tiles, hipStream_t s) {
-    // tiles per histogram workgroup: up to 8, never more than a node holds
-    const int64_t node_tiles = ((int64_t)kLeafSize << (h - j)) / kTile;
-    const int per = node_tiles < 8 ? (int)node_tiles : 8;
-    const unsigned hgrid = (unsigned)((tiles + per - 1) / per);
-    for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL((k_sel_hist<D, BITS>), dim3(hgrid), dim3(kThreads), 0, s, Xin, n, j, h, bj, hj, p, state,
-                           per);
-        hipLaunchKernelGGL((k_sel_pick<D, BITS>), dim3(1u << j), dim3(kThreads), 0, s, n, j, h, bj, hj, p, state);
-    }
-    hipLaunchKernelGGL((k_part_count<C, D, BITS>), dim3(grid), dim3(kThreads), 0, s, Xin, n, j, h, bj, state,
-                       split, cnt_less, cnt_eq, box, rel_box, split_hint, origin);
-    hipLaunchKernelGGL(k_part_scan, dim3(2), dim3(kScanThreads), 0, s, cnt_less, cnt_eq, (int)tiles);
-    hipLaunchKernelGGL((k_part_scatter<D>), dim3(grid), dim3(kThreads), 0, s, Xin, Iin, Xout, Iout, n, j, h, split,
-                       cnt_less, cnt_eq, tile_box);
-    hipLaunchKernelGGL((k_box_reduce<D>), dim3(1u << j), dim3(kThreads), 0, s, n, j, h, tile_box, bj1);
-}
-
 template <typename C, int D>
-dpc_status build_kd(const int32_t *points, Workspace &ws, Index &ix) {
+dpc_status build_kd(Workspace &ws, Index &ix) {
     hipStream_t s = ws.stream;
-    const int64_t n = ix.n;
-    const int h = ix.height;
-    const int jb = h > Bottom<D>::kLevels ? h - Bottom<D>::kLevels : 0;  // first bottom level
-    Origin origin{};
-    Spans spans{};
-    uint32_t widest = 0;
-    for (int k = 0; k < D; ++k) {
-        origin.v[k] = ix.lo[k];
-        spans.v[k] = (uint32_t)((int64_t)ix.hi[k] - (int64_t)ix.lo[k]);
-        widest = spans.v[k] > widest ? spans.v[k] : widest;
-    }
+    const int64_t np = ix.positions;
+    const int64_t tiles = np / kTile;
+    constexpr int W = (D + 1) / 2;
+    const bool single = ix.count == 1;
     C *coords, *box;
-    DPC_TRY(ws.alloc(&coords, (size_t)n * D));
-    DPC_TRY(ws.alloc(&box, (size_t)2 * ix.n_leaves * 2 * D));
-    DPC_TRY(ws.alloc(&ix.rbox, (size_t)2 * ix.n_leaves * 2 * D));
-    DPC_TRY(ws.alloc(&ix.sidx, n));
-    DPC_TRY(ws.alloc(&ix.split, (size_t)ix.n_leaves));
-    DPC_TRY(ws.alloc(&ix.leaf_org, (size_t)ix.n_leaves * D));
-    DPC_TRY(ws.alloc(&ix.leaf_ext, (size_t)ix.n_leaves));
-    DPC_TRY(ws.alloc(&ix.leaf_pack, (size_t)n * ((D + 1) / 2)));
+    DPC_TRY(ws.alloc(&coords, (size_t)np * D));
+    DPC_TRY(ws.alloc(&box, (size_t)ix.nodes * 2 * D));
+    DPC_TRY(ws.alloc(&ix.rbox, (size_t)ix.nodes * 2 * D));
+    DPC_TRY(ws.alloc(&ix.split, (size_t)ix.nodes));
+    DPC_TRY(ws.alloc(&ix.sidx, (size_t)np));
+    DPC_TRY(ws.alloc(&ix.leaf_org, (size_t)ix.leaves * D));
+    DPC_TRY(ws.alloc(&ix.leaf_ext, (size_t)ix.leaves));
+    DPC_TRY(ws.alloc(&ix.leaf_pack, (size_t)np * W));
     ix.coords = coords;
     ix.box = box;
 
-    uint32_t *XA, *XB, *IA, *IB;
-    DPC_TRY(ws.alloc(&XA, (size_t)D * n));
-    DPC_TRY(ws.alloc(&IA, n));
-    hipLaunchKernelGGL((k_soa_init<D>), dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, points, n, origin, XA,
-                       IA);
+    uint32_t *XA, *XB = nullptr, *IA, *IB = nullptr;
+    DPC_TRY(ws.alloc(&XA, (size_t)D * np));
+    DPC_TRY(ws.alloc(&IA, (size_t)np));
+    DPC_TRY(upload_group(ws, ix));
+    hipLaunchKernelGGL((k_soa_init<D>), dim3(blocks_for(np, kThreads)), dim3(kThreads), 0, s, ix.inst, ix.tile_inst,
+                       np, XA, IA);
     DPC_HIP(hipGetLastError());
-    if (jb > 0) {
-        DPC_TRY(ws.alloc(&XB, (size_t)D * n));
-        DPC_TRY(ws.alloc(&IB, n));
-        const int64_t tiles = (n + kTile - 1) / kTile;
-        const int wbits = widest ? 32 - __builtin_clz(widest) : 0;
-        // histogram words of every top level: passes x nodes x bins
-        int64_t hist_off[64];
-        int64_t hist_words = 0;
-        for (int j = 0; j < jb; ++j) {
-            const int bits = level_bits(j);
-            hist_off[j] = hist_words;
-            hist_words += (int64_t)((wbits + bits - 1) / bits) * (1ll << j) * (1ll << bits);
+
+    // host tables: histogram workgroups of every top level (groups only) and
+    // the LDS subtrees
+    std::vector<uint32_t> hist_blocks;
+    std::vector<int64_t> hist_first(ix.max_jb + 1, 0), node_first(ix.max_jb + 1, 0);
+    std::vector<uint2> subs, nodes;
+    for (int j = 0; j < ix.max_jb; ++j) {
+        hist_first[j] = (int64_t)hist_blocks.size();
+        node_first[j] = (int64_t)nodes.size();
+        if (single)
+            continue;
+        for (int i = 0; i < ix.count; ++i) {
+            const Inst &I = ix.host[i];
+            if (j >= I.jb)
+                continue;
+            const int64_t S = (int64_t)kLeafSize << (I.height - j);
+            for (int64_t t = 0; t * S < I.n; ++t)
+                nodes.push_back(make_uint2((uint32_t)i, (uint32_t)t));
         }
-        uint32_t *nboxes, *hist, *cnt_less, *cnt_eq;
-        NodeSplit *split;
+        for (const Inst &I : ix.host) {
+            if (j >= I.jb)
+                continue;
+            const int64_t node_tiles = ((int64_t)kLeafSize << (I.height - j)) / kTile;
+            const int64_t per = node_tiles < 8 ? node_tiles : 8;
+            const int64_t t_i = (I.n + kTile - 1) / kTile;
+            for (int64_t q = 0; q < t_i; q += per) {
+                const int64_t c = t_i - q < per ? t_i - q : per;
+                hist_blocks.push_back((uint32_t)(((I.P / kTile + q) << 4) | (c - 1)));
+            }
+        }
+    }
+    hist_first[ix.max_jb] = (int64_t)hist_blocks.size();
+    node_first[ix.max_jb] = (int64_t)nodes.size();
+    if (!single) {
+        for (int i = 0; i < ix.count; ++i) {
+            const Inst &I = ix.host[i];
+            const int64_t S0 = (int64_t)kLeafSize << (I.height - I.jb);
+            for (int64_t q = 0; q * S0 < I.n; ++q)
+                subs.push_back(make_uint2((uint32_t)i, (uint32_t)q));
+        }
+    }
+    uint32_t *d_hist_blocks = nullptr;
+    uint2 *d_subs = nullptr, *d_nodes = nullptr;
+    if (!single) {
+        DPC_TRY(ws.alloc(&d_hist_blocks, hist_blocks.size() + 1));
+        DPC_TRY(ws.alloc(&d_subs, subs.size() + 1));
+        DPC_TRY(ws.alloc(&d_nodes, nodes.size() + 1));
+        if (!hist_blocks.empty())
+            DPC_HIP(hipMemcpyAsync(d_hist_blocks, hist_blocks.data(), hist_blocks.size() * sizeof(uint32_t),
+                                   hipMemcpyHostToDevice, s));
+        if (!subs.empty())
+            DPC_HIP(hipMemcpyAsync(d_subs, subs.data(), subs.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
+        if (!nodes.empty())
+            DPC_HIP(hipMemcpyAsync(d_nodes, nodes.data(), nodes.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
+        DPC_HIP(hipStreamSynchronize(s));  // the host tables go out of scope
+    }
+
+    if (ix.max_jb > 0) {
+        DPC_TRY(ws.alloc(&XB, (size_t)D * np));
+        DPC_TRY(ws.alloc(&IB, (size_t)np));
+        int64_t nb_words = 0, hist_words = 0, sel = 0;
+        for (const Inst &I : ix.host) {
+            nb_words += I.jb > 0 ? (2ll << I.jb) * 2 * D : 0;
+            hist_words += hist_words_below(I.jb, I.wbits);
+            sel += I.jb > 0 ? 1ll << (I.jb - 1) : 0;
+        }
+        uint32_t *nboxes, *hist, *cnt_less, *cnt_eq, *tile_box;
+        NodeSplit *splits;
         SelectState *state;
-        const int64_t max_nodes = 1ll << (jb - 1);  // nodes of the deepest top level
-        DPC_TRY(ws.alloc(&nboxes, (size_t)(2ll << jb) * 2 * D));
+        DPC_TRY(ws.alloc(&nboxes, (size_t)nb_words));
         DPC_TRY(ws.alloc(&hist, (size_t)(hist_words > 0 ? hist_words : 1)));
-        DPC_TRY(ws.alloc(&split, (size_t)max_nodes));
-        DPC_TRY(ws.alloc(&state, (size_t)max_nodes));
+        DPC_TRY(ws.alloc(&splits, (size_t)sel));
+        DPC_TRY(ws.alloc(&state, (size_t)sel));
         DPC_TRY(ws.alloc(&cnt_less, (size_t)tiles));
         DPC_TRY(ws.alloc(&cnt_eq, (size_t)tiles));
-        uint32_t *tile_box;
         DPC_TRY(ws.alloc(&tile_box, (size_t)tiles * 4 * D));
         if (hist_words > 0)
             hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(hist_words, kThreads)), dim3(kThreads), 0, s, hist,
                                hist_words, 0u);
-        hipLaunchKernelGGL((k_root_box<D>), dim3(1), dim3(kWave), 0, s, nboxes + 2 * D, spans);
+        hipLaunchKernelGGL((k_root_box<D>), dim3(blocks_for(ix.count, kThreads)), dim3(kThreads), 0, s, ix.inst,
+                           ix.count, nboxes);
+        TopArrays A{XA, np, nboxes, hist, state, splits};
+        uint32_t *Iin = IA, *Xout = XB, *Iout = IB;  // level j reads buffer j mod 2
         const unsigned grid = (unsigned)tiles;
-        uint32_t *Xin = XA, *Xout = XB, *Iin = IA, *Iout = IB;
-        for (int j = 0; j < jb; ++j) {
-            const uint32_t *bj = nboxes + (1ll << j) * 2 * D;  // level j boxes start at heap index 2^j
-            uint32_t *bj1 = nboxes + (2ll << j) * 2 * D;
+        for (int j = 0; j < ix.max_jb; ++j) {
             const int bits = level_bits(j);
-            const int passes = (wbits + bits - 1) / bits;
+            const int passes = (ix.max_wbits + bits - 1) / bits;
+            // histogram workgroups: a table for groups; a fixed number of
+            // tiles each (up to 8, never more than a node holds) for one instance
+            const uint32_t *hb = nullptr;
+            const uint2 *nt = nullptr;
+            int per = 1;
+            unsigned hgrid, ngrid;
+            if (single) {
+                const int64_t node_tiles = ((int64_t)kLeafSize << (ix.host[0].height - j)) / kTile;
+                per = node_tiles < 8 ? (int)node_tiles : 8;
+                hgrid = (unsigned)((tiles + per - 1) / per);
+                ngrid = 1u << j;
+            } else {
+                hb = d_hist_blocks + hist_first[j];
+                hgrid = (unsigned)(hist_first[j + 1] - hist_first[j]);
+                nt = d_nodes + node_first[j];
+                ngrid = (unsigned)(node_first[j + 1] - node_first[j]);
+            }
+            for (int p = 0; p < passes; ++p) {
+                if (hgrid > 0) {
+                    if (bits == 11)
+                        hipLaunchKernelGGL((k_sel_hist<D, 11>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst,
+                                           ix.tile_inst, hb, per, A, j, p);
+                    else
+                        hipLaunchKernelGGL((k_sel_hist<D, 8>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst,
+                                           ix.tile_inst, hb, per, A, j, p);
+                }
+                if (bits == 11)
+                    hipLaunchKernelGGL((k_sel_pick<D, 11>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, p);
+                else
+                    hipLaunchKernelGGL((k_sel_pick<D, 8>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, p);
+            }
             if (bits == 11)
-                launch_level<C, D, 11>(Xin, Iin, Xout, Iout, n, j, h, passes, bj, bj1, hist + hist_off[j], state,
-                                       split, cnt_less, cnt_eq, tile_box, box, ix.rbox, ix.split, origin, grid, (unsigned)tiles, s);
+                hipLaunchKernelGGL((k_part_count<C, D, 11>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst,
+                                   A, j, cnt_less, cnt_eq, box, ix.rbox, ix.split);
             else
-                launch_level<C, D, 8>(Xin, Iin, Xout, Iout, n, j, h, passes, bj, bj1, hist + hist_off[j], state,
-                                      split, cnt_less, cnt_eq, tile_box, box, ix.rbox, ix.split, origin, grid, (unsigned)tiles, s);
+                hipLaunchKernelGGL((k_part_count<C, D, 8>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst,
+                                   A, j, cnt_less, cnt_eq, box, ix.rbox, ix.split);
+            hipLaunchKernelGGL(k_part_scan, dim3(2), dim3(kScanThreads), 0, s, cnt_less, cnt_eq, (int)tiles);
+            hipLaunchKernelGGL((k_part_scatter<D>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, A, Iin,
+                               Xout, Iout, j, cnt_less, cnt_eq, tile_box);
+            hipLaunchKernelGGL((k_box_reduce<D>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, tile_box);
             DPC_HIP(hipGetLastError());
-            uint32_t *t = Xin;
-            Xin = Xout;
+            uint32_t *t = A.X;
+            A.X = Xout;
             Xout = t;
             t = Iin;
             Iin = Iout;
             Iout = t;
         }
-        XA = Xin;
-        IA = Iin;
     }
-    hipLaunchKernelGGL((k_bottom<C, D>), dim3((unsigned)(1ll << jb)), dim3(kThreads), 0, s, XA, IA, n, jb, h, origin,
-                       box, ix.rbox, coords, ix.sidx, ix.leaf_org, ix.leaf_ext, ix.leaf_pack, ix.split);
+    const unsigned bgrid = single ? (unsigned)(1ll << ix.host[0].jb) : (unsigned)subs.size();
+    hipLaunchKernelGGL((k_bottom<C, D>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst, single ? nullptr : d_subs, XA, XB,
+                       IA, IB, np, box, ix.rbox, coords, ix.sidx, ix.leaf_org, ix.leaf_ext, ix.leaf_pack, ix.split);
     DPC_HIP(hipGetLastError());
     return DPC_OK;
 }
 
 }  // namespace
 
-dpc_status build_kdtree(const int32_t *points, Workspace &ws, Index &ix) {
+dpc_status build_kdtree(Workspace &ws, Index &ix) {
     const bool f64 = ix.arith == Arith::F64;
     switch (ix.d) {
 #define DPC_KD_CASE(DD) \
     case DD:            \
-        return f64 ? build_kd<double, DD>(points, ws, ix) : build_kd<int64_t, DD>(points, ws, ix);
+        return f64 ? build_kd<double, DD>(ws, ix) : build_kd<int64_t, DD>(ws, ix);
         DPC_KD_CASE(1)
         DPC_KD_CASE(2)
         DPC_KD_CASE(3)

@@ -28,8 +28,8 @@ def _declared():
 
 
 def test_header_declares_the_interface():
-    assert _declared() == sorted(["dpc_cluster", "dpc_density", "dpc_dependent", "dpc_last_stats", "dpc_run",
-                                  "dpc_square_threshold", "dpc_status_str"])
+    assert _declared() == sorted(["dpc_batch_run", "dpc_cluster", "dpc_density", "dpc_dependent", "dpc_last_stats",
+                                  "dpc_run", "dpc_square_threshold", "dpc_status_str"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -117,6 +117,15 @@ def test_argument_errors_before_any_device_work():
     assert _call("dpc_run", fake, 5, 0, 1.0, 0, 1.0, 0, fake, fake, fake, fake, NULL) == E
     assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 8, fake, fake, fake, fake, NULL) == E
     assert dpc.load().dpc_last_stats(None) == E
+    assert _call("dpc_batch_run", None, 3, 0, NULL) == E
+    assert _call("dpc_batch_run", None, -1, 0, NULL) == E
+    recs = (dpc.Instance * 2)()
+    assert _call("dpc_batch_run", recs, 2, 4, NULL) == E  # only the skip-noise flag is accepted
+    # every record invalid: nothing reaches the device, and each gets its status
+    recs[0] = dpc.Instance(0x1000, 5, 9, 1.0, 0, 1.0, 0x1000, 0x1000, 0x1000, 0x1000, -1)  # d out of range
+    recs[1] = dpc.Instance(0x1000, 5, 2, float("nan"), 0, 1.0, 0x1000, 0x1000, 0x1000, 0x1000, -1)
+    assert _call("dpc_batch_run", recs, 2, 0, NULL) == E
+    assert recs[0].status == E and recs[1].status == E
     with pytest.raises(dpc.DPCError):
         dpc.last_stats()  # no measured call on this thread
 
@@ -126,6 +135,10 @@ def test_empty_input_is_a_no_op():
     assert _call("dpc_dependent", NULL, 0, 3, NULL, 0, NULL, NULL, NULL) == 0
     assert _call("dpc_cluster", 0, NULL, NULL, NULL, 0, 1.0, NULL, NULL) == 0
     assert _call("dpc_run", NULL, 0, 8, 1.0, 0, 1.0, 1, NULL, NULL, NULL, NULL, NULL) == 0
+    assert _call("dpc_batch_run", None, 0, 0, NULL) == 0
+    recs = (dpc.Instance * 1)()
+    recs[0] = dpc.Instance(0, 0, 3, 1.0, 0, 1.0, 0, 0, 0, 0, -1)
+    assert _call("dpc_batch_run", recs, 1, 0, NULL) == 0 and recs[0].status == 0
 
 
 def test_product_path_has_no_oracle_or_fallback():

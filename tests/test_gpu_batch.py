@@ -1,0 +1,121 @@
+"""GPU parity of the batched call (dpc_batch_run).
+
+Every instance of a batch must get exactly the outputs dpc_run gives it
+alone, and small instances are checked against the CPU oracle directly.
+Batches mix dimensions, sizes across tile and subtree boundaries, both
+arithmetic paths, noise modes and failing instances.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import datagen  # noqa: E402
+import oracle  # noqa: E402
+import paper_2305_11335_amd as dpc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+
+
+def host(outs):
+    return [[t.cpu().numpy() for t in o] for o in outs]
+
+
+def same(got, want, what):
+    for name, g, w in zip(("rho", "dep", "delta2", "label"), got, want):
+        g, w = np.asarray(g), np.asarray(w)
+        if not np.array_equal(g, w):
+            i = int(np.flatnonzero(g != w)[0])
+            raise AssertionError(f"{what}: {name} differs at {int((g != w).sum())} places, first {i}: {g[i]} vs {w[i]}")
+
+
+def run_batch(problems, skip=False):
+    outs, st = dpc.batch_run([(dev(p), dc, rm, dm) for p, dc, rm, dm in problems], skip_noise=skip, check=False)
+    torch.cuda.synchronize()
+    return host(outs), st
+
+
+def small_problems(seed):
+    """Sizes across the leaf, subtree and tile boundaries in several dimensions."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    for n in (1, 2, 33, 500, 2047, 2049, 3000, 5000, 9000):
+        for d in (1, 2, 3, 5, 8):
+            if n > 3000 and d in (1, 5):
+                continue
+            pts = datagen.clustered_small(int(rng.integers(1 << 30)), n, d, span=1 << 16, k=4, sd_frac=0.02)
+            d_cut = float({1: 40, 2: 700, 3: 2500, 5: 9000, 8: 16000}[d])
+            probs.append((pts, d_cut, int(rng.integers(0, 6)), float(rng.choice([0.0, 2 * d_cut, 4 * d_cut]))))
+    rng.shuffle(probs)
+    return probs
+
+
+@pytest.mark.parametrize("skip", [False, True])
+def test_batch_small_against_oracle(skip):
+    probs = small_problems(11 + skip)
+    say("batch of", len(probs), "skip", skip)
+    got, st = run_batch(probs, skip)
+    assert st == [0] * len(probs)
+    for k, (p, dc, rm, dm) in enumerate(probs):
+        want = oracle.run(p, dc, rm, dm, skip)
+        same(got[k], want, f"instance {k} n={p.shape[0]} d={p.shape[1]}")
+
+
+def test_batch_equals_single_calls():
+    probs = [(x.points, x.d_cut, x.rho_min, x.delta_min)
+             for x in datagen.batch_instances(seed=9, count=48, n_hi=60_000)]
+    say("batch of", len(probs), "points", sum(p[0].shape[0] for p in probs))
+    got, st = run_batch(probs)
+    assert st == [0] * len(probs)
+    for k, (p, dc, rm, dm) in enumerate(probs):
+        alone = dpc.run(dev(p), dc, rm, dm)
+        torch.cuda.synchronize()
+        same(got[k], [t.cpu().numpy() for t in alone], f"instance {k} n={p.shape[0]} d={p.shape[1]}")
+
+
+def test_batch_failing_and_mixed_arithmetic():
+    ok1 = datagen.clustered_small(5, 3000, 2, span=1 << 16)
+    wide = np.array([[0, 0], [2**31 - 1, 2**31 - 1], [-2**31, -2**31]], np.int32)  # squared distances overflow int64
+    int64_path = datagen.random_small(6, 700, 1, 1 << 20)
+    int64_path[:2, 0] = [-1_500_000_000, 1_500_000_000]  # span 3e9: beyond 2^53 squared, int64 arithmetic
+    ok2 = datagen.clustered_small(7, 2500, 3, span=1 << 16)
+    empty = np.zeros((0, 2), np.int32)
+    probs = [(ok1, 700.0, 3, 2800.0), (wide, 1.0, 0, 1.0), (int64_path, 5000.0, 2, 20000.0), (ok2, 2500.0, 3, 1e4),
+             (empty, 1.0, 0, 1.0)]
+    got, st = run_batch(probs)
+    assert st == [0, 2, 0, 0, 0]
+    for k in (0, 2, 3):
+        p, dc, rm, dm = probs[k]
+        same(got[k], oracle.run(p, dc, rm, dm), f"instance {k}")
+
+
+def test_batch_full_workload():
+    """The 512-instance batch (n log-uniform in [1e3, 2e5], d in {2, 3, 5, 8}):
+    every instance equals its own dpc_run; a few small ones equal the oracle."""
+    insts = datagen.batch_instances()
+    probs = [(x.points, x.d_cut, x.rho_min, x.delta_min) for x in insts]
+    say("full batch", len(probs), "points", sum(p[0].shape[0] for p in probs))
+    got, st = run_batch(probs)
+    assert st == [0] * len(probs)
+    order = np.argsort([p[0].shape[0] for p in probs])
+    for k in range(len(probs)):
+        p, dc, rm, dm = probs[k]
+        alone = dpc.run(dev(p), dc, rm, dm)
+        torch.cuda.synchronize()
+        same(got[k], [t.cpu().numpy() for t in alone], f"instance {k} n={p.shape[0]} d={p.shape[1]}")
+    for k in order[:4]:
+        p, dc, rm, dm = probs[k]
+        say("oracle check", k, p.shape)
+        same(got[k], oracle.run(p, dc, rm, dm), f"instance {k} against the oracle")

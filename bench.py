@@ -10,7 +10,13 @@ average GPU time measured with HIP events on the launch stream during the
 timed steps; its algorithmic work from one extra instrumented run outside the
 timed region) and the plain O(n^2) CPU oracle timed on a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+A second measurement, "batched", runs the 512-instance workload (n
+log-uniform in [1e3, 2e5], d in {2, 3, 5, 8}) as one dpc_batch_run per step
+and, for comparison, as a loop of per-instance dpc_run calls on one stream
+and on four streams (one host thread each); outputs of the three are
+compared bit for bit.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-batch]
 """
 from __future__ import annotations
 
@@ -18,6 +24,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -79,6 +86,67 @@ def cpu_baseline(inst) -> dict:
                       f"{dt:.2f} s"}
 
 
+def batched(torch, dpc, datagen, steps: int) -> dict:
+    """Instances/s of the batched workload: one dpc_batch_run per step against
+    per-instance dpc_run loops (one stream; four streams driven by one host
+    thread each).  Inputs and outputs are resident; the three forms must give
+    identical outputs."""
+    insts = datagen.batch_instances()
+    dev = torch.device("cuda:0")
+    pts = [torch.from_numpy(x.points).to(dev) for x in insts]
+    probs = [(p, x.d_cut, x.rho_min, x.delta_min) for p, x in zip(pts, insts)]
+    total = sum(x.n for x in insts)
+    B = dpc.Batch(probs)
+    B.run()  # warm-up (pool growth, code loading)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.run()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+
+    outs = [tuple(torch.empty_like(t) for t in r) for r in B.results]
+
+    def loop(streams):
+        def work(k, s):
+            with torch.cuda.stream(s):
+                for i in range(k, len(probs), len(streams)):
+                    p, dc, rm, dm = probs[i]
+                    dpc.run(p, dc, rm, dm, out=outs[i], stream=s)
+            s.synchronize()
+
+        if len(streams) == 1:
+            work(0, streams[0])
+            return
+        th = [threading.Thread(target=work, args=(k, s)) for k, s in enumerate(streams)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+
+    timings = {}
+    for ns in (1, 4):
+        streams = [torch.cuda.Stream() for _ in range(ns)]
+        loop(streams)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loop(streams)
+        torch.cuda.synchronize()
+        timings[ns] = time.perf_counter() - t0
+        for r, o in zip(B.results, outs):
+            for a, b in zip(r, o):
+                if not torch.equal(a, b):
+                    raise RuntimeError("batched and per-instance outputs differ")
+    return {"workload": "batch512", "instances": len(insts), "points": total,
+            "dims": sorted({x.d for x in insts}), "steps": steps,
+            "instances_per_s": len(insts) / t_batch, "ms_per_batch": t_batch * 1000.0,
+            "points_per_s": total / t_batch,
+            "loop_1stream_instances_per_s": len(insts) / timings[1],
+            "loop_4streams_instances_per_s": len(insts) / timings[4],
+            "speedup_vs_best_loop": min(timings.values()) / t_batch,
+            "outputs_identical": True}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +154,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="varden2d_10m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -165,6 +235,8 @@ def main() -> int:
         "work": {k: work[k] for k in dpc.WORK_FIELDS},
         "roofline": roofline,
     }
+    if not args.no_batch:
+        rec["batched"] = batched(torch, dpc, datagen, args.batch_steps)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(rec), flush=True)

@@ -6,6 +6,7 @@ include/libdpc.h; this package is its thin Python binding.  See
 ``run`` take and return device tensors.
 """
 from ._binding import (  # noqa: F401
+    Batch,
     DPCError,
     Instance,
     EXPORTED,

@@ -215,6 +215,47 @@ def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool =
     return rho, dep, delta2, label
 
 
+class Batch:
+    """A prepared dpc_batch_run call: the instance records are built once, so
+    that repeated calls on the same tensors marshal nothing.
+
+    problems: sequence of (points, d_cut, rho_min, delta_min) with points an
+    int32 [n, d] device tensor; outs (optional) supplies the output tensors
+    [(rho, dep, delta2, label), ...].  The tensors must stay alive while the
+    batch is used."""
+
+    def __init__(self, problems, skip_noise: bool = False, outs=None):
+        torch = _torch()
+        self.count = len(problems)
+        self.recs = (Instance * max(self.count, 1))()
+        self.flags = SKIP_NOISE_DEPENDENTS if skip_noise else 0
+        self.points = []
+        self.results = []
+        for i, (points, d_cut, rho_min, delta_min) in enumerate(problems):
+            n, d = _check_points(points)
+            dev = points.device
+            o = outs[i] if outs is not None else (None, None, None, None)
+            rho = _out(o[0], n, torch.int32, dev)
+            dep = _out(o[1], n, torch.int32, dev)
+            delta2 = _out(o[2], n, torch.int64, dev)
+            label = _out(o[3], n, torch.int32, dev)
+            self.recs[i] = Instance(_ptr(points).value, n, d, float(d_cut), int(rho_min), float(delta_min),
+                                    _ptr(rho).value, _ptr(dep).value, _ptr(delta2).value, _ptr(label).value, -1)
+            self.points.append(points)
+            self.results.append((rho, dep, delta2, label))
+
+    def run(self, stream=None, check: bool = True):
+        """One dpc_batch_run over every instance; returns the call's status
+        (raises on failure with check)."""
+        st = load().dpc_batch_run(self.recs, self.count, self.flags, _stream(stream))
+        if check and st != OK:
+            raise DPCError(st, "dpc_batch_run")
+        return st
+
+    def statuses(self):
+        return [self.recs[i].status for i in range(self.count)]
+
+
 def batch_run(problems, skip_noise: bool = False, outs=None, stream=None, check: bool = True):
     """Runs many independent instances in one call.
 
@@ -222,23 +263,6 @@ def batch_run(problems, skip_noise: bool = False, outs=None, stream=None, check:
     int32 [n, d] device tensor.  Returns [(rho, dep, delta2, label), ...] and
     the per-instance statuses.  outs (optional) supplies the output tensors.
     With check, a failing instance raises."""
-    torch = _torch()
-    recs = (Instance * max(len(problems), 1))()
-    results = []
-    for i, (points, d_cut, rho_min, delta_min) in enumerate(problems):
-        n, d = _check_points(points)
-        dev = points.device
-        o = outs[i] if outs is not None else (None, None, None, None)
-        rho = _out(o[0], n, torch.int32, dev)
-        dep = _out(o[1], n, torch.int32, dev)
-        delta2 = _out(o[2], n, torch.int64, dev)
-        label = _out(o[3], n, torch.int32, dev)
-        recs[i] = Instance(_ptr(points).value, n, d, float(d_cut), int(rho_min), float(delta_min), _ptr(rho).value,
-                           _ptr(dep).value, _ptr(delta2).value, _ptr(label).value, -1)
-        results.append((rho, dep, delta2, label))
-    flags = SKIP_NOISE_DEPENDENTS if skip_noise else 0
-    st = load().dpc_batch_run(recs, len(problems), flags, _stream(stream))
-    statuses = [recs[i].status for i in range(len(problems))]
-    if check and st != OK:
-        raise DPCError(st, "dpc_batch_run")
-    return results, statuses
+    b = Batch(problems, skip_noise, outs)
+    b.run(stream, check)
+    return b.results, b.statuses()

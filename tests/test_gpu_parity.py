@@ -275,7 +275,7 @@ def test_deterministic_across_runs_and_streams():
         assert torch.equal(x, y.cpu()) and torch.equal(x, z)
 
 
-@pytest.mark.parametrize("name", ["varden2d_1m", "varden2d_10m", "uniform2d_10m"])
+@pytest.mark.parametrize("name", ["varden2d_1m", "varden2d_10m", "uniform2d_10m", "mix3d_10m", "aniso8d_10m"])
 def test_full_size_sampled(name):
     inst = datagen.make(name)
     say("full size", name, inst.n, inst.d, inst.d_cut)

@@ -16,7 +16,16 @@ and, for comparison, as a loop of per-instance dpc_run calls on one stream
 and on four streams (one host thread each); outputs of the three are
 compared bit for bit.
 
+A third, "served", replays a Poisson arrival stream (200 requests/s, n
+log-uniform in [1e3, 1e6], d = 3, uniform or clustered; requests drawn from a
+resident pool of 64 instances) through a dpc_server (HBM budget 200 GB) and
+reports p50/p99 latency (completion minus scheduled arrival) and throughput,
+beside the same trace run as plain per-request dpc_run calls in arrival
+order; each pool instance's served outputs are compared with its dpc_run
+outputs.
+
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-batch]
+                    [--no-serve] [--serve-seconds S]
 """
 from __future__ import annotations
 
@@ -147,6 +156,111 @@ def batched(torch, dpc, datagen, steps: int) -> dict:
             "outputs_identical": True}
 
 
+def served(torch, dpc, datagen, seconds: float, warm: float, rate: float = 200.0,
+           budget: int = 200 * 10**9) -> dict:
+    """p50/p99 latency and throughput of a Poisson request stream, through the
+    server and through plain per-request dpc_run calls (same trace)."""
+    import queue
+
+    import numpy as np
+
+    pool = datagen.served_instances()
+    dev = torch.device("cuda:0")
+    pts = [torch.from_numpy(x.points).to(dev) for x in pool]
+    rng = np.random.default_rng(55)
+    horizon = warm + seconds
+    gaps = rng.exponential(1.0 / rate, size=int(rate * horizon * 1.5) + 16)
+    arrivals = np.cumsum(gaps)
+    arrivals = arrivals[arrivals < horizon]
+    which = rng.integers(0, len(pool), size=len(arrivals))
+    first = {}  # pool entry -> outputs of its first served request
+    for k, w in enumerate(which):
+        first.setdefault(int(w), k)
+
+    def replay(submit, collect):
+        """Submits at the scheduled times from one thread; collect() runs in
+        this one, in submission order.  Returns (arrival_ns, done_ns) per request."""
+        q = queue.Queue()
+        t0 = time.monotonic_ns() + 50_000_000
+        sched = [t0 + int(a * 1e9) for a in arrivals]
+
+        def producer():
+            for k, w in enumerate(which):
+                dt = (sched[k] - time.monotonic_ns()) / 1e9
+                if dt > 0:
+                    time.sleep(dt)
+                q.put((k, submit(k, int(w))))
+            q.put(None)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        done = [0] * len(arrivals)
+        while True:
+            item = q.get()
+            if item is None:
+                break
+            k, h = item
+            done[k] = collect(k, h)
+        th.join()
+        return sched, done
+
+    def stats(sched, done, nbytes=None):
+        lat = []
+        pts_done = 0
+        t_lo = sched[0] + int(warm * 1e9)
+        for k in range(len(sched)):
+            if sched[k] >= t_lo:
+                lat.append((done[k] - sched[k]) / 1e6)
+                pts_done += pool[int(which[k])].n
+        lat = np.array(lat)
+        span = (max(done) - t_lo) / 1e9
+        return {"requests": len(lat), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "max_ms": float(lat.max()), "requests_per_s": len(lat) / span,
+                "points_per_s": pts_done / span}
+
+    # the server: outputs per request (kept for the pool entries' first requests)
+    outs = {}
+    with dpc.Server(hbm_budget_bytes=budget, slots=4, max_batch=64) as srv:
+        def submit_srv(k, w):
+            x = pool[w]
+            t, res = srv.submit(pts[w], x.d_cut, x.rho_min, x.delta_min)
+            if first[w] == k:
+                outs[w] = res
+            return t
+
+        sched, done = replay(submit_srv, lambda k, t: srv.wait(t)["done_ns"])
+        sst = srv.stats()
+    rec = {"workload": "served_poisson200_3d", "rate_req_per_s": rate, "seconds": seconds, "warmup_s": warm,
+           "pool_instances": len(pool), "hbm_budget_bytes": budget, "slots": 4, "max_batch": 64,
+           "server": stats(sched, done),
+           "server_stats": {k: sst[k] for k in ("batches", "max_batch_seen", "max_slots_busy", "max_admitted_bytes",
+                                                "max_workspace_bytes", "over_footprint")}}
+
+    # plain per-request dpc_run calls on one stream, in arrival order
+    s = torch.cuda.Stream()
+
+    def submit_plain(k, w):
+        return w
+
+    def collect_plain(k, w):
+        x = pool[w]
+        dpc.run(pts[w], x.d_cut, x.rho_min, x.delta_min, stream=s)
+        s.synchronize()
+        return time.monotonic_ns()
+
+    sched, done = replay(submit_plain, collect_plain)
+    rec["plain_loop"] = stats(sched, done)
+    for w, res in outs.items():
+        x = pool[w]
+        alone = dpc.run(pts[w], x.d_cut, x.rho_min, x.delta_min)
+        for a, b in zip(res, alone):
+            if not torch.equal(a, b):
+                raise RuntimeError("served and alone outputs differ")
+    torch.cuda.synchronize()
+    rec["outputs_identical_to_alone"] = True
+    return rec
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +270,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-workload measurement")
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-warmup", type=float, default=3.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -236,8 +353,14 @@ def main() -> int:
         "roofline": roofline,
     }
     if not args.no_batch:
+        print("bench: batched workload", file=sys.stderr, flush=True)
         rec["batched"] = batched(torch, dpc, datagen, args.batch_steps)
+    if not args.no_serve:
+        print(f"bench: served workload ({args.serve_warmup + args.serve_seconds:.0f} s, twice)", file=sys.stderr,
+              flush=True)
+        rec["served"] = served(torch, dpc, datagen, args.serve_seconds, args.serve_warmup)
     if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(rec), flush=True)
     return 0

@@ -114,6 +114,7 @@ typedef struct {
     int64_t density_wave_points;   /* leaf points iterated over (some lane tests them), density step */
     int64_t dependent_wave_nodes;  /* nodes visited, dependent step */
     int64_t dependent_wave_points; /* leaf points iterated over, dependent step */
+    uint64_t workspace_bytes;      /* device workspace the call allocated (each allocation rounded up to 256 B) */
 } dpc_stats;
 
 /*
@@ -200,6 +201,89 @@ typedef struct {
  * instances once (synchronising the stream).
  */
 DPC_API int dpc_batch_run(dpc_instance *instances, int32_t count, uint32_t flags, hipStream_t stream);
+
+/*
+ * Upper bound on the device workspace (bytes, as the library counts them:
+ * each allocation rounded up to 256 B) that dpc_run or dpc_batch_run takes
+ * for an instance of n points in d dimensions; a batch takes at most the sum
+ * of its instances' bounds.  The caller's inputs and outputs are not
+ * included.  Host only; 0 for an invalid shape.
+ */
+DPC_API uint64_t dpc_workspace_bytes(int64_t n, int32_t d);
+
+/*
+ * Served clustering (the batching of dpc_batch_run applied to a stream of
+ * requests).  A server owns `slots` host threads, each with a HIP stream of
+ * its own on the device current at creation.  Requests wait in one queue in
+ * arrival order; whenever a slot is free it takes the longest prefix of the
+ * queue (at most max_batch requests) whose workspace bounds
+ * (dpc_workspace_bytes), added to those of the requests already running,
+ * stay within hbm_budget_bytes, and runs it as one batch.  A request that
+ * arrives while batches run thus joins the next batch a slot forms, and
+ * several batches overlap on the device.  Every request's outputs are
+ * bit-identical to those of dpc_run with the same arguments, whatever it is
+ * batched with.
+ */
+typedef struct dpc_server dpc_server; /* opaque */
+
+typedef struct {
+    uint64_t hbm_budget_bytes; /* > 0: bound on the summed workspace bounds of the requests in flight */
+    int32_t slots;             /* 1 .. 16: batches in flight at once */
+    int32_t max_batch;         /* >= 1: requests per batch */
+} dpc_server_config;
+
+typedef struct {
+    int32_t done;        /* 1 once the request's outputs are written and its device work has completed */
+    int32_t status;      /* when done: the dpc_status dpc_run would return for it (or a runtime error) */
+    int64_t submit_ns;   /* CLOCK_MONOTONIC times of submission, admission to a batch and completion */
+    int64_t admit_ns;
+    int64_t done_ns;
+    uint64_t footprint;  /* workspace bound charged against the budget while it ran */
+    int32_t batch_size;  /* requests in its batch */
+    int32_t slot;        /* the slot that ran it */
+} dpc_request_info;
+
+typedef struct {
+    int64_t submitted;            /* requests accepted */
+    int64_t completed;            /* requests done */
+    int64_t rejected;             /* requests refused because their bound exceeds the whole budget */
+    int64_t batches;              /* batches started */
+    int64_t max_batch_seen;       /* largest batch */
+    int32_t max_slots_busy;       /* most batches in flight at once */
+    uint64_t max_admitted_bytes;  /* largest summed bound of the requests in flight */
+    uint64_t max_workspace_bytes; /* largest workspace a batch held */
+    int64_t over_footprint;       /* batches whose workspace exceeded their summed bound (a library bug if > 0) */
+    uint64_t in_flight_bytes;     /* now: summed bound of the requests in flight */
+    int64_t queued;               /* now: requests waiting */
+} dpc_server_stats;
+
+/* Creates a server on the current device.  DPC_ERR_INVALID_ARG for a NULL
+ * argument or a configuration outside the ranges above. */
+DPC_API int dpc_server_create(const dpc_server_config *config, dpc_server **out);
+
+/*
+ * Queues one request: a record as for dpc_batch_run (device pointers; status
+ * is ignored) and flags 0 or DPC_SKIP_NOISE_DEPENDENTS.  The arrays must stay
+ * valid and untouched until the request is done.  Argument errors are
+ * returned at once (no ticket); DPC_ERR_OOM if the request's bound alone
+ * exceeds the budget.  Otherwise *ticket identifies the request.
+ */
+DPC_API int dpc_server_submit(dpc_server *server, const dpc_instance *request, uint32_t flags, uint64_t *ticket);
+
+/* Copies the request's state into *info without blocking.  Once a poll or
+ * wait has reported it done, the ticket is forgotten (later calls with it
+ * return DPC_ERR_INVALID_ARG). */
+DPC_API int dpc_server_poll(dpc_server *server, uint64_t ticket, dpc_request_info *info);
+
+/* Blocks until the request is done, then as dpc_server_poll. */
+DPC_API int dpc_server_wait(dpc_server *server, uint64_t ticket, dpc_request_info *info);
+
+/* Counters since creation. */
+DPC_API int dpc_server_get_stats(dpc_server *server, dpc_server_stats *out);
+
+/* Runs every queued request to completion, then stops the slots and frees
+ * the server.  Results of requests not yet waited for are discarded. */
+DPC_API int dpc_server_destroy(dpc_server *server);
 
 /*
  * Diagnostics: copies the measurements of the calling thread's most recent

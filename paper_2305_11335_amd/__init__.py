@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     LIB_PATH,
     SKIP_NOISE_DEPENDENTS,
     STAGES,
+    Server,
     WORK_FIELDS,
     batch_run,
     cluster,
@@ -24,4 +25,5 @@ from ._binding import (  # noqa: F401
     run,
     square_threshold,
     status_str,
+    workspace_bytes,
 )

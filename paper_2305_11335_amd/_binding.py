@@ -21,7 +21,9 @@ INF = (1 << 63) - 1
 STAGES = ("index", "density", "priority", "dependent", "labels")
 
 EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_batch_run", "dpc_last_stats",
-            "dpc_status_str", "dpc_square_threshold")
+            "dpc_status_str", "dpc_square_threshold", "dpc_workspace_bytes", "dpc_server_create",
+            "dpc_server_submit", "dpc_server_poll", "dpc_server_wait", "dpc_server_get_stats",
+            "dpc_server_destroy")
 
 
 class Stats(ctypes.Structure):
@@ -30,7 +32,7 @@ class Stats(ctypes.Structure):
                 ("density_contained", ctypes.c_int64), ("dependent_pairs", ctypes.c_int64),
                 ("dependent_nodes", ctypes.c_int64), ("density_wave_nodes", ctypes.c_int64),
                 ("density_wave_points", ctypes.c_int64), ("dependent_wave_nodes", ctypes.c_int64),
-                ("dependent_wave_points", ctypes.c_int64)]
+                ("dependent_wave_points", ctypes.c_int64), ("workspace_bytes", ctypes.c_uint64)]
 
 WORK_FIELDS = ("density_pairs", "density_nodes", "density_contained", "dependent_pairs", "dependent_nodes",
                "density_wave_nodes", "density_wave_points", "dependent_wave_nodes", "dependent_wave_points")
@@ -41,6 +43,24 @@ class Instance(ctypes.Structure):
                 ("d_cut", ctypes.c_double), ("rho_min", ctypes.c_int32), ("delta_min", ctypes.c_double),
                 ("rho", ctypes.c_void_p), ("dep", ctypes.c_void_p), ("delta2", ctypes.c_void_p),
                 ("label", ctypes.c_void_p), ("status", ctypes.c_int32)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("submit_ns", ctypes.c_int64),
+                ("admit_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64), ("footprint", ctypes.c_uint64),
+                ("batch_size", ctypes.c_int32), ("slot", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("max_batch_seen", ctypes.c_int64), ("max_slots_busy", ctypes.c_int32),
+                ("max_admitted_bytes", ctypes.c_uint64), ("max_workspace_bytes", ctypes.c_uint64),
+                ("over_footprint", ctypes.c_int64), ("in_flight_bytes", ctypes.c_uint64),
+                ("queued", ctypes.c_int64)]
 
 
 _lib = None
@@ -77,6 +97,20 @@ def load():
     lib.dpc_batch_run.restype = ctypes.c_int
     lib.dpc_last_stats.argtypes = [ctypes.POINTER(Stats)]
     lib.dpc_last_stats.restype = ctypes.c_int
+    lib.dpc_workspace_bytes.argtypes = [i64, i32]
+    lib.dpc_workspace_bytes.restype = ctypes.c_uint64
+    lib.dpc_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
+    lib.dpc_server_create.restype = ctypes.c_int
+    lib.dpc_server_submit.argtypes = [P, ctypes.POINTER(Instance), u32, ctypes.POINTER(ctypes.c_uint64)]
+    lib.dpc_server_submit.restype = ctypes.c_int
+    lib.dpc_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(RequestInfo)]
+    lib.dpc_server_poll.restype = ctypes.c_int
+    lib.dpc_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(RequestInfo)]
+    lib.dpc_server_wait.restype = ctypes.c_int
+    lib.dpc_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    lib.dpc_server_get_stats.restype = ctypes.c_int
+    lib.dpc_server_destroy.argtypes = [P]
+    lib.dpc_server_destroy.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -188,6 +222,7 @@ def last_stats() -> dict:
         raise DPCError(st, "dpc_last_stats")
     out = {"flags": s.flags, "stage_ms": dict(zip(STAGES, list(s.stage_ms)))}
     out.update({k: getattr(s, k) for k in WORK_FIELDS})
+    out["workspace_bytes"] = s.workspace_bytes
     return out
 
 
@@ -266,3 +301,86 @@ def batch_run(problems, skip_noise: bool = False, outs=None, stream=None, check:
     b = Batch(problems, skip_noise, outs)
     b.run(stream, check)
     return b.results, b.statuses()
+
+
+def workspace_bytes(n: int, d: int) -> int:
+    """Upper bound on the device workspace of one instance (dpc_workspace_bytes)."""
+    return int(load().dpc_workspace_bytes(int(n), int(d)))
+
+
+def _info(ri) -> dict:
+    return {f: getattr(ri, f) for f, _ in RequestInfo._fields_}
+
+
+class Server:
+    """A dpc_server: requests are queued with submit() and run in batches on
+    `slots` streams as the HBM budget allows (see include/libdpc.h).
+
+    The tensors of a request are kept referenced until its result has been
+    collected with poll() or wait()."""
+
+    def __init__(self, hbm_budget_bytes: int, slots: int = 2, max_batch: int = 64):
+        self._h = ctypes.c_void_p()
+        cfg = ServerConfig(int(hbm_budget_bytes), int(slots), int(max_batch))
+        st = load().dpc_server_create(ctypes.byref(cfg), ctypes.byref(self._h))
+        if st != OK:
+            raise DPCError(st, "dpc_server_create")
+        self._keep = {}
+
+    def submit(self, points, d_cut: float, rho_min: int, delta_min: float, out=None, skip_noise: bool = False):
+        """Queues one request; returns (ticket, (rho, dep, delta2, label))."""
+        torch = _torch()
+        n, d = _check_points(points)
+        dev = points.device
+        o = out if out is not None else (None, None, None, None)
+        res = (_out(o[0], n, torch.int32, dev), _out(o[1], n, torch.int32, dev), _out(o[2], n, torch.int64, dev),
+               _out(o[3], n, torch.int32, dev))
+        rec = Instance(_ptr(points).value, n, d, float(d_cut), int(rho_min), float(delta_min), _ptr(res[0]).value,
+                       _ptr(res[1]).value, _ptr(res[2]).value, _ptr(res[3]).value, -1)
+        t = ctypes.c_uint64()
+        st = load().dpc_server_submit(self._h, ctypes.byref(rec), SKIP_NOISE_DEPENDENTS if skip_noise else 0,
+                                      ctypes.byref(t))
+        if st != OK:
+            raise DPCError(st, "dpc_server_submit")
+        self._keep[t.value] = (points, res)
+        return t.value, res
+
+    def poll(self, ticket: int):
+        """The request's state (a dict; 'done' 0 or 1) without blocking."""
+        ri = RequestInfo()
+        st = load().dpc_server_poll(self._h, ticket, ctypes.byref(ri))
+        if st != OK:
+            raise DPCError(st, "dpc_server_poll")
+        if ri.done:
+            self._keep.pop(ticket, None)
+        return _info(ri)
+
+    def wait(self, ticket: int) -> dict:
+        """Blocks until the request is done; returns its state."""
+        ri = RequestInfo()
+        st = load().dpc_server_wait(self._h, ticket, ctypes.byref(ri))
+        if st != OK:
+            raise DPCError(st, "dpc_server_wait")
+        self._keep.pop(ticket, None)
+        return _info(ri)
+
+    def stats(self) -> dict:
+        ss = ServerStats()
+        st = load().dpc_server_get_stats(self._h, ctypes.byref(ss))
+        if st != OK:
+            raise DPCError(st, "dpc_server_get_stats")
+        return {f: getattr(ss, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            st = load().dpc_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+            if st != OK:
+                raise DPCError(st, "dpc_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -101,6 +101,7 @@ struct ThreadStats {
     int device = -1;
     hipEvent_t ev[DPC_STAGES + 1] = {};
     int64_t counters[kCounters] = {};
+    uint64_t workspace_bytes = 0;
 };
 
 thread_local ThreadStats t_stats;
@@ -141,9 +142,10 @@ class RunRecorder {
         DPC_HIP(hipStreamSynchronize(stream_));
         return DPC_OK;
     }
-    void commit() {
+    void commit(size_t workspace_bytes) {
         if (flags_ == 0)
             return;
+        t_stats.workspace_bytes = workspace_bytes;
         if (!(flags_ & DPC_COUNT_WORK))
             for (auto &c : t_stats.counters)
                 c = 0;
@@ -172,6 +174,7 @@ class RunRecorder {
         out->density_wave_points = t_stats.counters[kDensityWavePoints];
         out->dependent_wave_nodes = t_stats.counters[kDependentWaveNodes];
         out->dependent_wave_points = t_stats.counters[kDependentWavePoints];
+        out->workspace_bytes = t_stats.workspace_bytes;
         return DPC_OK;
     }
 
@@ -244,6 +247,75 @@ dpc_status run_group(const std::vector<Job> &jobs, int d, Arith arith, RunRecord
 }
 
 }  // namespace
+
+dpc_status check_instance(const dpc_instance &q, uint32_t flags) {
+    Job J;
+    return make_job(q.points, q.n, q.d, q.d_cut, q.rho_min, q.delta_min, flags, q.rho, q.dep, q.delta2, q.label, J);
+}
+
+// Every step for a list of instances (each with its own flags: 0 or
+// DPC_SKIP_NOISE_DEPENDENTS), grouped by dimension and arithmetic; sets each
+// record's status.  peak_bytes (optional): the largest workspace held at
+// once.
+dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int count, hipStream_t stream,
+                         size_t *peak_bytes) {
+    size_t peak = 0;
+    // checks, then groups by dimension
+    std::vector<std::vector<int>> by_d(kMaxDim + 1);
+    std::vector<Job> all(count);
+    int first_error = DPC_OK;
+    for (int i = 0; i < count; ++i) {
+        dpc_instance &q = instances[i];
+        q.status = make_job(q.points, q.n, q.d, q.d_cut, q.rho_min, q.delta_min, flags[i], q.rho, q.dep,
+                            q.delta2, q.label, all[i]);
+        if (q.status == DPC_OK && q.n > 0)
+            by_d[q.d].push_back(i);
+        if (q.status != DPC_OK && first_error == DPC_OK)
+            first_error = q.status;
+    }
+    for (int d = 1; d <= kMaxDim; ++d) {
+        if (by_d[d].empty())
+            continue;
+        std::vector<Job> jobs;
+        for (int i : by_d[d])
+            jobs.push_back(all[i]);
+        std::vector<int> bad;
+        {
+            Workspace ws(stream);
+            const dpc_status st = job_bounds(jobs, d, ws, &bad);
+            peak = ws.bytes > peak ? ws.bytes : peak;
+            if (st != DPC_OK && st != DPC_ERR_RANGE)
+                return st;
+        }
+        for (int b : bad) {
+            instances[by_d[d][b]].status = DPC_ERR_RANGE;
+            if (first_error == DPC_OK)
+                first_error = DPC_ERR_RANGE;
+        }
+        // one group per arithmetic
+        for (int a = 0; a < 2; ++a) {
+            const Arith arith = a == 0 ? Arith::F64 : Arith::I64;
+            std::vector<Job> group;
+            for (size_t k = 0; k < jobs.size(); ++k) {
+                if (instances[by_d[d][k]].status != DPC_OK || job_arith(jobs[k], d) != arith)
+                    continue;
+                group.push_back(jobs[k]);
+            }
+            if (!group.empty()) {
+                Workspace ws(stream);
+                const dpc_status st = run_group(group, d, arith, nullptr, nullptr, ws);
+                peak = ws.bytes > peak ? ws.bytes : peak;
+                if (st != DPC_OK)
+                    return st;
+            }
+        }
+    }
+    if (peak_bytes)
+        *peak_bytes = peak;
+    return (dpc_status)first_error;
+}
+
+
 }  // namespace dpc
 
 using namespace dpc;
@@ -350,60 +422,21 @@ int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t r
     DPC_TRY(run_group(jobs, d, job_arith(jobs[0], d), &rec, counters, ws));
     if (counters)
         DPC_TRY(rec.read_counters(counters));
-    rec.commit();
+    rec.commit(ws.bytes);
     return DPC_OK;
 }
 
 int dpc_batch_run(dpc_instance *instances, int32_t count, uint32_t flags, hipStream_t stream) {
     if (count < 0 || (count > 0 && instances == nullptr) || (flags & ~(uint32_t)DPC_SKIP_NOISE_DEPENDENTS))
         return DPC_ERR_INVALID_ARG;
-    // checks, then groups by dimension
-    std::vector<std::vector<int>> by_d(kMaxDim + 1);
-    std::vector<Job> all(count);
-    int first_error = DPC_OK;
-    for (int i = 0; i < count; ++i) {
-        dpc_instance &q = instances[i];
-        q.status = make_job(q.points, q.n, q.d, q.d_cut, q.rho_min, q.delta_min, flags, q.rho, q.dep, q.delta2,
-                            q.label, all[i]);
-        if (q.status == DPC_OK && q.n > 0)
-            by_d[q.d].push_back(i);
-        if (q.status != DPC_OK && first_error == DPC_OK)
-            first_error = q.status;
-    }
-    for (int d = 1; d <= kMaxDim; ++d) {
-        if (by_d[d].empty())
-            continue;
-        std::vector<Job> jobs;
-        for (int i : by_d[d])
-            jobs.push_back(all[i]);
-        std::vector<int> bad;
-        {
-            Workspace ws(stream);
-            const dpc_status st = job_bounds(jobs, d, ws, &bad);
-            if (st != DPC_OK && st != DPC_ERR_RANGE)
-                return st;
-        }
-        for (int b : bad) {
-            instances[by_d[d][b]].status = DPC_ERR_RANGE;
-            if (first_error == DPC_OK)
-                first_error = DPC_ERR_RANGE;
-        }
-        // one group per arithmetic
-        for (int a = 0; a < 2; ++a) {
-            const Arith arith = a == 0 ? Arith::F64 : Arith::I64;
-            std::vector<Job> group;
-            for (size_t k = 0; k < jobs.size(); ++k) {
-                if (instances[by_d[d][k]].status != DPC_OK || job_arith(jobs[k], d) != arith)
-                    continue;
-                group.push_back(jobs[k]);
-            }
-            if (!group.empty()) {
-                Workspace ws(stream);
-                DPC_TRY(run_group(group, d, arith, nullptr, nullptr, ws));
-            }
-        }
-    }
-    return first_error;
+    std::vector<uint32_t> fl((size_t)count, flags);
+    return run_instances(instances, fl.data(), count, stream, nullptr);
+}
+
+uint64_t dpc_workspace_bytes(int64_t n, int32_t d) {
+    if (bad_shape(n, d))
+        return 0;
+    return workspace_bound(n, d);
 }
 
 int dpc_last_stats(dpc_stats *out) {

@@ -133,6 +133,7 @@ struct Workspace {
     static constexpr int kCap = 160;
     void *ptrs[kCap];
     int count = 0;
+    size_t bytes = 0;  // allocated so far, each allocation rounded up to 256 bytes
     hipMemPool_t pool;
     explicit Workspace(hipStream_t s) : stream(s), pool(workspace_pool()) {}
     ~Workspace() { release(); }
@@ -142,15 +143,14 @@ struct Workspace {
         if (count >= kCap)
             return DPC_ERR_OOM;
         void *p = nullptr;
-        size_t bytes = elems * sizeof(T);
-        if (bytes == 0)
-            bytes = 256;
-        const hipError_t e = pool ? hipMallocFromPoolAsync(&p, bytes, pool, stream) : hipMallocAsync(&p, bytes, stream);
+        const size_t want = bytes_rounded(elems * sizeof(T));
+        const hipError_t e = pool ? hipMallocFromPoolAsync(&p, want, pool, stream) : hipMallocAsync(&p, want, stream);
         if (e != hipSuccess || p == nullptr) {
             (void)hipGetLastError();
             return DPC_ERR_OOM;
         }
         ptrs[count++] = p;
+        bytes += want;
         *out = static_cast<T *>(p);
         return DPC_OK;
     }
@@ -159,6 +159,7 @@ struct Workspace {
             (void)hipFreeAsync(ptrs[i], stream);
         count = 0;
     }
+    static size_t bytes_rounded(size_t b) { return ((b == 0 ? 256 : b) + 255) & ~(size_t)255; }
 };
 
 #define DPC_HIP(call)                                      \
@@ -206,6 +207,11 @@ __device__ inline const Inst &inst_of_tile(const Inst *__restrict__ inst, const 
     return inst[tile_inst ? tile_inst[tile] : 0u];
 }
 
+// Upper bound on the workspace bytes (as Workspace::bytes counts them) of one
+// instance of n points in d dimensions, alone or as part of a group: a
+// group's workspace is at most the sum of its instances' bounds.
+uint64_t workspace_bound(int64_t n, int d);
+
 // Exact thresholds (host).
 dpc_status square_threshold(double r, bool round_up, int64_t *out);
 
@@ -246,6 +252,15 @@ dpc_status launch_cluster(int64_t n, const int32_t *rho, const int32_t *dep, con
                           int32_t rho_min, int64_t Td, bool validate, int32_t *label, Workspace &ws);
 // labels of every instance of a group (the edges come from its own outputs)
 dpc_status launch_group_labels(const Index &ix, Workspace &ws);
+
+// api.hip: every step for a list of instances, each with its own flags (0 or
+// DPC_SKIP_NOISE_DEPENDENTS); sets each record's status and returns the first
+// failure.  peak_bytes (optional) receives the largest workspace held at once.
+dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int count, hipStream_t stream,
+                         size_t *peak_bytes);
+
+// The argument checks of dpc_run for one instance (host only).
+dpc_status check_instance(const dpc_instance &q, uint32_t flags);
 
 // Kernel-launch geometry helpers.
 inline unsigned blocks_for(int64_t items, int per_block) {

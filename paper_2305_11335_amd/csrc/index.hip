@@ -364,6 +364,39 @@ Arith job_arith(const Job &J, int d) {
     return sum < ((unsigned __int128)1 << 53) ? Arith::F64 : Arith::I64;
 }
 
+uint64_t workspace_bound(int64_t n, int d) {
+    if (n <= 0)
+        return 0;
+    const uint64_t D = (uint64_t)d, W = (D + 1) / 2;
+    const uint64_t Pn = (uint64_t)padded(n), tiles = Pn / kTile;
+    const int h = tree_height(n);
+    const uint64_t leaves = 1ull << h, nodes = 2 * leaves;
+    const int jb = h > bottom_levels(d) ? h - bottom_levels(d) : 0;
+    uint64_t b = 0;
+    // per position: coords (8 bytes per axis), the two relative-coordinate
+    // and index buffers of the build, the original index, the packed leaf
+    // offsets, the key, the sorted density and the label parents
+    b += Pn * (8 * D + 2 * 4 * D + 2 * 4 + 4 + 4 * W + 8 + 4 + 4);
+    // per node: box, relative box, split hint, maximum key; per leaf: corner and width
+    b += nodes * (16 * D + 8 * D + 8 + 8) + leaves * (4 * D + 4);
+    // top levels: node boxes, histograms (widest coordinates: 32 bits), select records
+    b += (2ull << jb) * 2 * D * 4;
+    for (int l = 0; l < jb; ++l) {
+        const int bits = l <= 8 ? 11 : 8;
+        b += (uint64_t)((32 + bits - 1) / bits) * (1ull << l) * (1ull << bits) * 4;
+    }
+    b += (jb > 0 ? 1ull << (jb - 1) : 0) * 32;
+    // per tile: partition counts, tile boxes, the tile table and tile bounds
+    b += tiles * (4 + 4 + 16 * D + 4 + 2 * kMaxDim * 4);
+    // descriptor, bounds, work tables of the top levels and subtrees
+    b += sizeof(Inst) + 2 * kMaxDim * 4 + 4 * (uint64_t)jb * (tiles + 1) + 8 * 2 * ((1ull << jb) + 1);
+    // the instrumented kernels' counters and the labels' flag
+    b += kCounters * 8 + 8;
+    // rounding of every allocation
+    b += (uint64_t)Workspace::kCap * 256;
+    return b;
+}
+
 dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, Workspace &ws, Index &ix) {
     hipStream_t s = ws.stream;
     ix.d = d;

@@ -29,7 +29,9 @@ def _declared():
 
 def test_header_declares_the_interface():
     assert _declared() == sorted(["dpc_batch_run", "dpc_cluster", "dpc_density", "dpc_dependent", "dpc_last_stats",
-                                  "dpc_run", "dpc_square_threshold", "dpc_status_str"])
+                                  "dpc_run", "dpc_square_threshold", "dpc_status_str", "dpc_workspace_bytes",
+                                  "dpc_server_create", "dpc_server_submit", "dpc_server_poll", "dpc_server_wait",
+                                  "dpc_server_get_stats", "dpc_server_destroy"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -152,3 +154,42 @@ def test_product_path_has_no_oracle_or_fallback():
                     src = fh.read()
                 assert "import oracle" not in src and "from oracle" not in src, f
                 assert "dpc_oracle" not in src, f
+
+
+def test_workspace_bound_is_host_only_and_grows_with_n():
+    assert dpc.workspace_bytes(0, 2) == 0
+    assert dpc.workspace_bytes(-1, 2) == 0 and dpc.workspace_bytes(10, 0) == 0 and dpc.workspace_bytes(10, 9) == 0
+    for d in (1, 2, 3, 5, 8):
+        prev = 0
+        for n in (1, 1000, 2048, 2049, 100_000, 1_000_000, 10_000_000):
+            b = dpc.workspace_bytes(n, d)
+            # at least the sorted coordinates, the two build buffers, keys and indices
+            assert b >= n * (16 * d + 24), (n, d, b)
+            assert b >= prev
+            prev = b
+    # linear in n at scale (per point, within 25% between 2^20 and 2^23)
+    for d in (2, 3, 8):
+        a = dpc.workspace_bytes(1 << 20, d) / (1 << 20)
+        b = dpc.workspace_bytes(1 << 23, d) / (1 << 23)
+        assert 0.8 < a / b < 1.25
+
+
+def test_server_argument_errors():
+    lib = dpc.load()
+    h = ctypes.c_void_p()
+    assert lib.dpc_server_create(None, ctypes.byref(h)) == dpc._binding.ERR_INVALID_ARG
+    for cfg in (dpc._binding.ServerConfig(0, 1, 1), dpc._binding.ServerConfig(1 << 30, 0, 1),
+                dpc._binding.ServerConfig(1 << 30, 17, 1), dpc._binding.ServerConfig(1 << 30, 2, 0)):
+        assert lib.dpc_server_create(ctypes.byref(cfg), ctypes.byref(h)) == dpc._binding.ERR_INVALID_ARG
+        assert not h.value
+    cfg = dpc._binding.ServerConfig(1 << 30, 1, 1)
+    assert lib.dpc_server_create(ctypes.byref(cfg), None) == dpc._binding.ERR_INVALID_ARG
+    info = dpc._binding.RequestInfo()
+    ss = dpc._binding.ServerStats()
+    t = ctypes.c_uint64()
+    rec = dpc.Instance()
+    assert lib.dpc_server_submit(None, ctypes.byref(rec), 0, ctypes.byref(t)) == dpc._binding.ERR_INVALID_ARG
+    assert lib.dpc_server_poll(None, 1, ctypes.byref(info)) == dpc._binding.ERR_INVALID_ARG
+    assert lib.dpc_server_wait(None, 1, ctypes.byref(info)) == dpc._binding.ERR_INVALID_ARG
+    assert lib.dpc_server_get_stats(None, ctypes.byref(ss)) == dpc._binding.ERR_INVALID_ARG
+    assert lib.dpc_server_destroy(None) == dpc._binding.ERR_INVALID_ARG

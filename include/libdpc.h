@@ -167,6 +167,34 @@ DPC_API int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, i
             int32_t *label, hipStream_t stream);
 
 /*
+ * Parameter sweeps (the decision-graph workflow of Section 3: the outputs for
+ * many parameter values, each step reusing what does not depend on them).
+ *
+ * dpc_density_sweep: the density of every point for count radii, building
+ * the spatial index once (it does not depend on d_cut).
+ *   d_cuts  host array of count radii (each as for dpc_density).
+ *   rho     int32 [count][n] device: row k is dpc_density with d_cuts[k].
+ * Synchronises the stream once more at the end.
+ */
+DPC_API int dpc_density_sweep(const int32_t *points, int64_t n, int32_t d, const double *d_cuts, int32_t count,
+                              int32_t *rho, hipStream_t stream);
+
+/*
+ * dpc_cluster_sweep: labels for count (rho_min, delta_min) pairs from one
+ * (rho, dep, delta2) (delta_min touches only this step, Definition 5; rho_min
+ * only the noise test of Definition 4, with dependents computed for every
+ * point).
+ *   rho_mins, delta_mins  host arrays of count values (each as for
+ *                         dpc_cluster); 0 <= count <= 65535.
+ *   label   int32 [count][n] device: row k is dpc_cluster with pair k.
+ * Every followed edge of every pair is checked as in dpc_cluster
+ * (DPC_ERR_NOT_FOREST); synchronises the stream once for that check.
+ */
+DPC_API int dpc_cluster_sweep(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2,
+                              const int32_t *rho_mins, const double *delta_mins, int32_t count, int32_t *label,
+                              hipStream_t stream);
+
+/*
  * One independent clustering problem of a batch: the arguments and output
  * arrays of dpc_run, plus the instance's own status (written).
  */

@@ -18,7 +18,9 @@ from ._binding import (  # noqa: F401
     WORK_FIELDS,
     batch_run,
     cluster,
+    cluster_sweep,
     density,
+    density_sweep,
     dependent,
     last_stats,
     load,

@@ -21,7 +21,8 @@ INF = (1 << 63) - 1
 STAGES = ("index", "density", "priority", "dependent", "labels")
 
 EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_batch_run", "dpc_last_stats",
-            "dpc_status_str", "dpc_square_threshold", "dpc_workspace_bytes", "dpc_server_create",
+            "dpc_status_str", "dpc_square_threshold", "dpc_workspace_bytes", "dpc_density_sweep",
+            "dpc_cluster_sweep", "dpc_server_create",
             "dpc_server_submit", "dpc_server_poll", "dpc_server_wait", "dpc_server_get_stats",
             "dpc_server_destroy")
 
@@ -97,6 +98,10 @@ def load():
     lib.dpc_batch_run.restype = ctypes.c_int
     lib.dpc_last_stats.argtypes = [ctypes.POINTER(Stats)]
     lib.dpc_last_stats.restype = ctypes.c_int
+    lib.dpc_density_sweep.argtypes = [P, i64, i32, ctypes.POINTER(dbl), i32, P, P]
+    lib.dpc_density_sweep.restype = ctypes.c_int
+    lib.dpc_cluster_sweep.argtypes = [i64, P, P, P, ctypes.POINTER(i32), ctypes.POINTER(dbl), i32, P, P]
+    lib.dpc_cluster_sweep.restype = ctypes.c_int
     lib.dpc_workspace_bytes.argtypes = [i64, i32]
     lib.dpc_workspace_bytes.restype = ctypes.c_uint64
     lib.dpc_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
@@ -248,6 +253,37 @@ def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool =
     if st != OK:
         raise DPCError(st, "dpc_run")
     return rho, dep, delta2, label
+
+
+def density_sweep(points, d_cuts, out=None, stream=None):
+    """rho for several radii ([len(d_cuts), n] int32), one index build."""
+    torch = _torch()
+    n, d = _check_points(points)
+    k = len(d_cuts)
+    rho = out if out is not None else torch.empty((k, n), dtype=torch.int32, device=points.device)
+    if rho.dtype != torch.int32 or tuple(rho.shape) != (k, n) or not rho.is_contiguous():
+        raise TypeError(f"out must be a contiguous int32 [{k}, {n}] tensor")
+    arr = (ctypes.c_double * max(k, 1))(*[float(x) for x in d_cuts])
+    st = load().dpc_density_sweep(_ptr(points), n, d, arr, k, _ptr(rho), _stream(stream))
+    if st != OK:
+        raise DPCError(st, "dpc_density_sweep")
+    return rho
+
+
+def cluster_sweep(rho, dep, delta2, pairs, out=None, stream=None):
+    """Labels for several (rho_min, delta_min) pairs ([len(pairs), n] int32)."""
+    torch = _torch()
+    n = rho.numel()
+    k = len(pairs)
+    label = out if out is not None else torch.empty((k, n), dtype=torch.int32, device=rho.device)
+    if label.dtype != torch.int32 or tuple(label.shape) != (k, n) or not label.is_contiguous():
+        raise TypeError(f"out must be a contiguous int32 [{k}, {n}] tensor")
+    rm = (ctypes.c_int32 * max(k, 1))(*[int(p[0]) for p in pairs])
+    dm = (ctypes.c_double * max(k, 1))(*[float(p[1]) for p in pairs])
+    st = load().dpc_cluster_sweep(n, _ptr(rho), _ptr(dep), _ptr(delta2), rm, dm, k, _ptr(label), _stream(stream))
+    if st != OK:
+        raise DPCError(st, "dpc_cluster_sweep")
+    return label
 
 
 class Batch:

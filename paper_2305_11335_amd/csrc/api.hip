@@ -399,6 +399,70 @@ int dpc_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t
     return launch_cluster(n, rho, dep, delta2, rho_min, Td, true, label, ws);
 }
 
+int dpc_density_sweep(const int32_t *points, int64_t n, int32_t d, const double *d_cuts, int32_t count, int32_t *rho,
+                      hipStream_t stream) {
+    if (bad_shape(n, d) || count < 0 || (count > 0 && d_cuts == nullptr))
+        return DPC_ERR_INVALID_ARG;
+    std::vector<int64_t> T((size_t)count);
+    for (int k = 0; k < count; ++k)
+        if (std::isnan(d_cuts[k]) || d_cuts[k] < 0.0 || square_threshold(d_cuts[k], false, &T[k]) != DPC_OK)
+            return DPC_ERR_INVALID_ARG;
+    if (n > 0 && count > 0 && (points == nullptr || rho == nullptr))
+        return DPC_ERR_INVALID_ARG;
+    if (n == 0 || count == 0)
+        return DPC_OK;
+    // one index for every radius: the tree does not depend on d_cut
+    Job J;
+    J.points = points;
+    J.n = n;
+    J.rho = rho;
+    J.T = T[0];
+    Workspace ws(stream);
+    std::vector<Job> jobs{J};
+    DPC_TRY(job_bounds(jobs, d, ws, nullptr));
+    Index ix;
+    DPC_TRY(build_group(jobs, d, job_arith(jobs[0], d), ws, ix));
+    int32_t *srho;
+    DPC_TRY(ws.alloc(&srho, (size_t)ix.positions));
+    // one descriptor per radius, each writing its own row of rho
+    std::vector<Inst> desc((size_t)count, ix.host[0]);
+    for (int k = 0; k < count; ++k) {
+        density_params(desc[k], T[k], d);
+        desc[k].rho = rho + (int64_t)k * n;
+    }
+    Inst *d_desc;
+    DPC_TRY(ws.alloc(&d_desc, (size_t)count));
+    DPC_HIP(hipMemcpyAsync(d_desc, desc.data(), count * sizeof(Inst), hipMemcpyHostToDevice, stream));
+    for (int k = 0; k < count; ++k) {
+        Index one = ix;
+        one.inst = d_desc + k;
+        one.host.assign(1, desc[k]);
+        one.intbox = ix.arith == Arith::F64 && desc[k].limit >= 0;
+        DPC_TRY(launch_density(one, srho, nullptr, stream));
+    }
+    DPC_HIP(hipStreamSynchronize(stream));  // the host descriptors go out of scope
+    return DPC_OK;
+}
+
+int dpc_cluster_sweep(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2,
+                      const int32_t *rho_mins, const double *delta_mins, int32_t count, int32_t *label,
+                      hipStream_t stream) {
+    if (n < 0 || n > (int64_t)std::numeric_limits<int32_t>::max() - 1 || count < 0 || count > 65535)
+        return DPC_ERR_INVALID_ARG;
+    if (count > 0 && (rho_mins == nullptr || delta_mins == nullptr))
+        return DPC_ERR_INVALID_ARG;
+    std::vector<int64_t> Td((size_t)count);
+    for (int k = 0; k < count; ++k)
+        if (rho_mins[k] < 0 || delta_threshold(delta_mins[k], &Td[k]) != DPC_OK)
+            return DPC_ERR_INVALID_ARG;
+    if (n > 0 && count > 0 && (rho == nullptr || dep == nullptr || delta2 == nullptr || label == nullptr))
+        return DPC_ERR_INVALID_ARG;
+    if (n == 0 || count == 0)
+        return DPC_OK;
+    Workspace ws(stream);
+    return launch_cluster_sweep(n, rho, dep, delta2, count, rho_mins, Td.data(), label, ws);
+}
+
 int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
             uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2, int32_t *label, hipStream_t stream) {
     const uint32_t known = DPC_SKIP_NOISE_DEPENDENTS | DPC_TIME_STAGES | DPC_COUNT_WORK;

@@ -125,6 +125,71 @@ __global__ __launch_bounds__(kThreads) void k_roots_group(const Inst *__restrict
     I.label[i] = x;
 }
 
+// One parent array per parameter pair (blockIdx.y), with the checks of
+// k_parent; flag[k] is set when pair k follows an edge that does not rise.
+__global__ __launch_bounds__(kThreads) void k_parent_sweep(int64_t n, const int32_t *__restrict__ rho,
+                                                           const int32_t *__restrict__ dep,
+                                                           const int64_t *__restrict__ delta2,
+                                                           const int32_t *__restrict__ rho_mins,
+                                                           const int64_t *__restrict__ Tds, int32_t *__restrict__ par,
+                                                           int32_t *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= n)
+        return;
+    const int32_t r = rho[i];
+    int32_t p = (int32_t)i;
+    if (r >= rho_mins[k] && delta2[i] < Tds[k]) {
+        const int32_t j = dep[i];
+        bool ok = j >= 0 && (int64_t)j < n;
+        if (ok) {
+            const int32_t rj = rho[j];
+            ok = rj > r || (rj == r && (int64_t)j < i);
+        }
+        if (ok)
+            p = j;
+        else
+            __hip_atomic_store(flag + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    par[(int64_t)k * n + i] = p;
+}
+
+__global__ __launch_bounds__(kThreads) void k_roots_sweep(int64_t n, const int32_t *__restrict__ rho,
+                                                          const int32_t *__restrict__ rho_mins, int32_t *par_all,
+                                                          int32_t *__restrict__ label_all) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= n)
+        return;
+    int32_t *label = label_all + (int64_t)k * n;
+    if (rho[i] < rho_mins[k]) {
+        label[i] = -1;
+        return;
+    }
+    int32_t *par = par_all + (int64_t)k * n;
+    int32_t x = (int32_t)i;
+    // every followed edge rises (checked), so a chain has fewer than n edges
+    for (int64_t steps = 0; steps <= n; ++steps) {
+        const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == x)
+            break;
+        const int32_t g = __hip_atomic_load(&par[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (g == p) {
+            x = p;
+            break;
+        }
+        __hip_atomic_store(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = g;
+    }
+    label[i] = x;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t count, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        p[i] = v;
+}
+
 }  // namespace
 
 dpc_status launch_group_labels(const Index &ix, Workspace &ws) {
@@ -157,6 +222,34 @@ dpc_status launch_cluster(int64_t n, const int32_t *rho, const int32_t *dep, con
             return DPC_ERR_NOT_FOREST;
     }
     hipLaunchKernelGGL(k_roots, grid, block, 0, s, n, rho, rho_min, par, label, flag);
+    DPC_HIP(hipGetLastError());
+    return DPC_OK;
+}
+
+dpc_status launch_cluster_sweep(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2, int count,
+                                const int32_t *rho_mins, const int64_t *Tds, int32_t *label, Workspace &ws) {
+    hipStream_t s = ws.stream;
+    int32_t *par, *flag, *d_rmin;
+    int64_t *d_Td;
+    DPC_TRY(ws.alloc(&par, (size_t)n * count));
+    DPC_TRY(ws.alloc(&flag, (size_t)count));
+    DPC_TRY(ws.alloc(&d_rmin, (size_t)count));
+    DPC_TRY(ws.alloc(&d_Td, (size_t)count));
+    DPC_HIP(hipMemcpyAsync(d_rmin, rho_mins, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    DPC_HIP(hipMemcpyAsync(d_Td, Tds, count * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(count, kThreads)), dim3(kThreads), 0, s, flag, (int64_t)count, 0);
+    const dim3 grid(blocks_for(n, kThreads), (unsigned)count), block(kThreads);
+    hipLaunchKernelGGL(k_parent_sweep, grid, block, 0, s, n, rho, dep, delta2, d_rmin, d_Td, par, flag);
+    DPC_HIP(hipGetLastError());
+    // an unchecked cycle would never let the walks end: check first (this
+    // also keeps the host parameter arrays alive until they are copied)
+    std::vector<int32_t> h((size_t)count, 0);
+    DPC_HIP(hipMemcpyAsync(h.data(), flag, count * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DPC_HIP(hipStreamSynchronize(s));
+    for (int32_t f : h)
+        if (f != 0)
+            return DPC_ERR_NOT_FOREST;
+    hipLaunchKernelGGL(k_roots_sweep, grid, block, 0, s, n, rho, d_rmin, par, label);
     DPC_HIP(hipGetLastError());
     return DPC_OK;
 }

@@ -207,6 +207,11 @@ __device__ inline const Inst &inst_of_tile(const Inst *__restrict__ inst, const 
     return inst[tile_inst ? tile_inst[tile] : 0u];
 }
 
+// The density threshold T of an instance and the clamped integer parameters
+// derived from it (M, R, limit: limit < 0 when the integer comparisons do
+// not apply).
+void density_params(Inst &I, int64_t T, int d);
+
 // Upper bound on the workspace bytes (as Workspace::bytes counts them) of one
 // instance of n points in d dimensions, alone or as part of a group: a
 // group's workspace is at most the sum of its instances' bounds.
@@ -252,6 +257,10 @@ dpc_status launch_cluster(int64_t n, const int32_t *rho, const int32_t *dep, con
                           int32_t rho_min, int64_t Td, bool validate, int32_t *label, Workspace &ws);
 // labels of every instance of a group (the edges come from its own outputs)
 dpc_status launch_group_labels(const Index &ix, Workspace &ws);
+// labels of one instance for count parameter pairs (rows of label), with
+// every followed edge checked
+dpc_status launch_cluster_sweep(int64_t n, const int32_t *rho, const int32_t *dep, const int64_t *delta2, int count,
+                                const int32_t *rho_mins, const int64_t *Tds, int32_t *label, Workspace &ws);
 
 // api.hip: every step for a list of instances, each with its own flags (0 or
 // DPC_SKIP_NOISE_DEPENDENTS); sets each record's status and returns the first

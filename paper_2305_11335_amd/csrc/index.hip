@@ -364,6 +364,20 @@ Arith job_arith(const Job &J, int d) {
     return sum < ((unsigned __int128)1 << 53) ? Arith::F64 : Arith::I64;
 }
 
+void density_params(Inst &I, int64_t T, int d) {
+    // the clamped integer comparisons need M <= R, where d * R^2 < 2^31 and
+    // R < 2^15
+    I.T = T;
+    I.r = isqrt64(T);
+    const int64_t R0 = isqrt64((int64_t)std::numeric_limits<int32_t>::max() / d);
+    const int64_t R = R0 < 32767 ? R0 : 32767;
+    const int64_t M = I.r + 1;
+    I.R = (int32_t)R;
+    I.M = (int32_t)(M <= R ? M : R + 1);
+    I.limit = M <= R ? (int32_t)(R - M) : -1;
+    I.Tn = M <= R ? (int32_t)T : 0;
+}
+
 uint64_t workspace_bound(int64_t n, int d) {
     if (n <= 0)
         return 0;
@@ -435,17 +449,7 @@ dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, Workspa
         H += hw;
         S += I.jb > 0 ? 1ll << (I.jb - 1) : 0;
         B += I.jb > 0 ? (2ll << I.jb) * 2 * d : 0;
-        // density thresholds; the clamped integer comparisons need M <= R,
-        // where d * R^2 < 2^31 and R < 2^15
-        I.T = J.T;
-        I.r = isqrt64(J.T);
-        const int64_t R0 = isqrt64((int64_t)std::numeric_limits<int32_t>::max() / d);
-        const int64_t R = R0 < 32767 ? R0 : 32767;
-        const int64_t M = I.r + 1;
-        I.R = (int32_t)R;
-        I.M = (int32_t)(M <= R ? M : R + 1);
-        I.limit = M <= R ? (int32_t)(R - M) : -1;
-        I.Tn = M <= R ? (int32_t)J.T : 0;
+        density_params(I, J.T, d);
         if (I.limit < 0)
             ix.intbox = false;
         I.dep_rho_min = J.dep_rho_min;

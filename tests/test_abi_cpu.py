@@ -30,6 +30,7 @@ def _declared():
 def test_header_declares_the_interface():
     assert _declared() == sorted(["dpc_batch_run", "dpc_cluster", "dpc_density", "dpc_dependent", "dpc_last_stats",
                                   "dpc_run", "dpc_square_threshold", "dpc_status_str", "dpc_workspace_bytes",
+                                  "dpc_density_sweep", "dpc_cluster_sweep",
                                   "dpc_server_create", "dpc_server_submit", "dpc_server_poll", "dpc_server_wait",
                                   "dpc_server_get_stats", "dpc_server_destroy"])
 
@@ -193,3 +194,22 @@ def test_server_argument_errors():
     assert lib.dpc_server_wait(None, 1, ctypes.byref(info)) == dpc._binding.ERR_INVALID_ARG
     assert lib.dpc_server_get_stats(None, ctypes.byref(ss)) == dpc._binding.ERR_INVALID_ARG
     assert lib.dpc_server_destroy(None) == dpc._binding.ERR_INVALID_ARG
+
+
+def test_sweep_argument_errors():
+    lib = dpc.load()
+    E = dpc._binding.ERR_INVALID_ARG
+    dc = (ctypes.c_double * 2)(1.0, float("nan"))
+    # a NaN radius, a negative count, d out of range: rejected before device work
+    assert lib.dpc_density_sweep(None, 10, 2, dc, 2, None, None) == E
+    assert lib.dpc_density_sweep(None, 10, 2, dc, -1, None, None) == E
+    assert lib.dpc_density_sweep(None, 10, 9, dc, 1, None, None) == E
+    assert lib.dpc_density_sweep(None, 10, 2, dc, 1, None, None) == E  # null arrays
+    assert lib.dpc_density_sweep(None, 0, 2, dc, 1, None, None) == 0   # n = 0: nothing to do
+    assert lib.dpc_density_sweep(None, 10, 2, None, 0, None, None) == 0  # no radii
+    rm = (ctypes.c_int32 * 2)(1, -1)
+    dm = (ctypes.c_double * 2)(1.0, 2.0)
+    assert lib.dpc_cluster_sweep(10, None, None, None, rm, dm, 2, None, None) == E  # negative rho_min
+    assert lib.dpc_cluster_sweep(10, None, None, None, rm, dm, 1, None, None) == E  # null arrays
+    assert lib.dpc_cluster_sweep(10, None, None, None, rm, dm, 65536, None, None) == E
+    assert lib.dpc_cluster_sweep(0, None, None, None, rm, dm, 1, None, None) == 0

@@ -8,7 +8,10 @@ method), with the points already resident in HBM.  The workload is the
 Prints one JSON line: throughput, the roofline of the dominant kernel (its
 average GPU time measured with HIP events on the launch stream during the
 timed steps; its algorithmic work from one extra instrumented run outside the
-timed region) and the plain O(n^2) CPU oracle timed on a bounded sample.
+timed region), the plain O(n^2) CPU oracle timed on a bounded sample
+("cpu_baseline") and the multithreaded CPU k-d tree version on the whole
+workload with all allowed host threads ("cpu_parallel", outputs compared with
+the GPU's).
 
 A second measurement, "batched", runs the 512-instance workload (n
 log-uniform in [1e3, 2e5], d in {2, 3, 5, 8}) as one dpc_batch_run per step
@@ -93,6 +96,23 @@ def cpu_baseline(inst) -> dict:
             "sample": f"first {m} points of {inst.name} (input order is a seeded shuffle), d_cut scaled by "
                       f"(n/m)^(1/d) to {d_cut:.3f} for the same expected density; whole method, one thread, "
                       f"{dt:.2f} s"}
+
+
+def cpu_parallel(inst, gpu_out) -> dict:
+    """The multithreaded CPU baseline (k-d tree, all allowed host threads) on
+    the whole workload; its outputs must equal the GPU's."""
+    import numpy as np
+
+    import cpu_baseline
+
+    threads = cpu_baseline.threads_available()
+    t0 = time.perf_counter()
+    got = cpu_baseline.run(inst.points, inst.d_cut, inst.rho_min, inst.delta_min, threads=threads)
+    dt = time.perf_counter() - t0
+    same = all(np.array_equal(a, b.cpu().numpy()) for a, b in zip(got, gpu_out))
+    return {"value": inst.n / dt, "unit": "points/s", "cores": threads, "kind": "cpu_kdtree_multithreaded",
+            "sample": f"whole {inst.name} ({inst.n} points), one run, {dt:.2f} s",
+            "outputs_identical_to_gpu": bool(same)}
 
 
 def batched(torch, dpc, datagen, steps: int) -> dict:
@@ -267,7 +287,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="varden2d_10m")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip both CPU baselines")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-workload measurement")
@@ -362,6 +382,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(inst)
+        print("bench: multithreaded CPU baseline", file=sys.stderr, flush=True)
+        rec["cpu_parallel"] = cpu_parallel(inst, out)
     print(json.dumps(rec), flush=True)
     return 0
 

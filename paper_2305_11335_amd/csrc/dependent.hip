@@ -59,6 +59,8 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                                                         int64_t *__restrict__ delta2_out, int64_t *counters,
                                                         const Inst *__restrict__ inst,
                                                         const uint32_t *__restrict__ tile_inst) {
+    __shared__ C s_pts[kThreads / kWave][kLeafSize * D];
+    __shared__ uint64_t s_key[kThreads / kWave][kLeafSize];
     uint64_t n_pairs = 0, n_nodes = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
     int64_t q0 = wave_base(kThreads);
@@ -125,34 +127,32 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
             if (v >= first_leaf) {
                 if (STATS && __ballot(want) != 0)
                     w_points += (uint64_t)count;
-                if (want) {
-                    // keys and coordinates are wave-uniform: load a batch,
-                    // then test it
-                    constexpr int kBatch = D <= 2 ? 4 : (D <= 4 ? 2 : 1);  // within the scalar registers
-                    const C *p = coords + start * D;
-                    const uint64_t *kp = skey + start;
-                    int t = 0;
-                    for (; t + kBatch <= (int)count; t += kBatch) {
-                        uint64_t kb[kBatch];
-                        C qb[kBatch][D];
-#pragma unroll
-                        for (int b = 0; b < kBatch; ++b) {
-                            kb[b] = kp[t + b];
-#pragma unroll
-                            for (int k = 0; k < D; ++k)
-                                qb[b][k] = p[(t + b) * D + k];
-                        }
-#pragma unroll
-                        for (int b = 0; b < kBatch; ++b)
-                            consider<C, D, STATS>(x, qb[b], kb[b], kq, best, best_low, n_pairs);
-                    }
-                    for (; t < (int)count; ++t) {
-                        C qv[D];
+                if (__ballot(want) != 0) {
+                    // the wave stages the leaf in its LDS slot (one coalesced
+                    // load), then the lanes that want it read every point
+                    // from there (same address for all lanes: a broadcast)
+                    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+                    C *sp = s_pts[w];
+                    uint64_t *sk = s_key[w];
+                    if (lane < count) {
 #pragma unroll
                         for (int k = 0; k < D; ++k)
-                            qv[k] = p[t * D + k];
-                        consider<C, D, STATS>(x, qv, kp[t], kq, best, best_low, n_pairs);
+                            sp[lane * D + k] = coords[(start + lane) * D + k];
+                        sk[lane] = skey[start + lane];
                     }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (want) {
+                        for (int t = 0; t < (int)count; ++t) {
+                            C qv[D];
+#pragma unroll
+                            for (int k = 0; k < D; ++k)
+                                qv[k] = sp[t * D + k];
+                            consider<C, D, STATS>(x, qv, sk[t], kq, best, best_low, n_pairs);
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
                 }
             } else {
                 const uint64_t m = __ballot(want);

@@ -50,24 +50,34 @@ struct Narrow {
 };
 
 // Points of one leaf within distance^2 T of x.  The leaf's coordinates are
-// wave-uniform (scalar loads); a batch of kBatch points is loaded before any
-// is used so that the loads overlap.
-template <typename C, int D, int kMaxBatch = 8>
+// wave-uniform: scalar loads from global memory, or (kStaged) the wave's copy
+// in LDS, which every lane reads at the same address.  A batch of kBatch
+// points is read before any is used so that the reads overlap; the staged
+// loop is not unrolled further (its values live in vector registers).
+template <typename C, int D, int kBatch, bool kStaged>
 __device__ inline int32_t count_within(const C (&x)[D], const C *__restrict__ p, int count, C T) {
-    constexpr int kFit = D <= 2 ? 8 : (D <= 4 ? 4 : 2);  // within the scalar registers
-    constexpr int kBatch = kFit < kMaxBatch ? kFit : kMaxBatch;
-    int32_t c = 0;
-    int t = 0;
-    for (; t + kBatch <= count; t += kBatch) {
+    auto batch = [&](int t) {
         C q[kBatch][D];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b)
 #pragma unroll
             for (int k = 0; k < D; ++k)
                 q[b][k] = p[(t + b) * D + k];
+        int32_t c = 0;
 #pragma unroll
         for (int b = 0; b < kBatch; ++b)
             c += dist2<C, D>(x, q[b]) <= T ? 1 : 0;
+        return c;
+    };
+    int32_t c = 0;
+    int t = 0;
+    if constexpr (kStaged) {
+#pragma unroll 1
+        for (; t + kBatch <= count; t += kBatch)
+            c += batch(t);
+    } else {
+        for (; t + kBatch <= count; t += kBatch)
+            c += batch(t);
     }
     for (; t < count; ++t)
         c += point_dist2<C, D>(x, p + t * D) <= T ? 1 : 0;
@@ -76,23 +86,21 @@ __device__ inline int32_t count_within(const C (&x)[D], const C *__restrict__ p,
 
 // The same count on a narrow leaf: q holds the query's clamped offsets from
 // the leaf corner, packed like the leaf's points.
-template <int W>
+template <int W, int kBatch, bool kStaged>
 __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint32_t *__restrict__ p, int count,
                                               int32_t T) {
-    constexpr int kBatch = W == 1 ? 16 : (8 / W > 0 ? 8 / W : 1);  // within the scalar registers
     short2_t qv[W];
 #pragma unroll
     for (int w = 0; w < W; ++w)
         qv[w] = __builtin_bit_cast(short2_t, q[w]);
-    int32_t c = 0;
-    int t = 0;
-    for (; t + kBatch <= count; t += kBatch) {
+    auto batch = [&](int t) {
         uint32_t pb[kBatch][W];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b)
 #pragma unroll
             for (int w = 0; w < W; ++w)
                 pb[b][w] = p[(t + b) * W + w];
+        int32_t c = 0;
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             int32_t acc = 0;
@@ -103,6 +111,17 @@ __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint
             }
             c += acc <= T ? 1 : 0;
         }
+        return c;
+    };
+    int32_t c = 0;
+    int t = 0;
+    if constexpr (kStaged) {
+#pragma unroll 1
+        for (; t + kBatch <= count; t += kBatch)
+            c += batch(t);
+    } else {
+        for (; t + kBatch <= count; t += kBatch)
+            c += batch(t);
     }
     for (; t < count; ++t) {
         int32_t acc = 0;
@@ -162,6 +181,8 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
                                                       int64_t *counters) {
     constexpr bool kPacked = std::is_same<C, double>::value;
     constexpr int W = (D + 1) / 2;
+    // one staged leaf per wave: D 8-byte coordinates or W packed words per point
+    __shared__ uint64_t s_leaf[kThreads / kWave][D >= 3 ? kLeafSize * D : 1];
     uint64_t n_pairs = 0, n_nodes = 0, n_contained = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
     // this wave's instance; positions, nodes and leaves below are its own
@@ -239,33 +260,69 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
     int depth = sd;
 
     // Points of leaf v (positions [start, start + count)) within the radius,
-    // for the lanes to which the leaf is partial.
+    // for the lanes to which the leaf is partial.  From three dimensions on,
+    // the wave first stages the leaf in its LDS slot with coalesced loads (the
+    // packed offsets while the leaf's width is read; the coordinates when the
+    // leaf is wide) and the lanes read each point from there; below that the
+    // leaf is small enough for a few scalar loads.
+    constexpr bool kStage = D >= 3;
+    constexpr int kPackBatch = kStage ? 2 : (W == 1 ? 16 : 8 / W);
+    constexpr int kWideBatch = kStage ? 1 : (INTBOX ? 2 : 8);
     auto leaf_count = [&](uint32_t leaf, int64_t start, int64_t count, bool partial) {
-        if (STATS && __ballot(partial) != 0)
+        const bool any = __ballot(partial) != 0;
+        if (STATS && any)
             w_points += (uint64_t)count;
-        if (!partial)
+        if (!any)
             return;
-        if (STATS)
+        if (STATS && partial)
             n_pairs += (uint64_t)count;
         const uint32_t c = leaf - first_leaf;
-        bool narrow = false;
-        if constexpr (kPacked)
-            narrow = (int32_t)nw.ext[c] <= nw.limit;
-        if (narrow) {
-            uint32_t qw[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const int32_t a = clamp_i32(xi[2 * w] - (int32_t)nw.org[(size_t)c * D + 2 * w], -nw.M, nw.R);
-                const int32_t b =
-                    2 * w + 1 < D ? clamp_i32(xi[2 * w + 1] - (int32_t)nw.org[(size_t)c * D + 2 * w + 1], -nw.M, nw.R)
-                                  : 0;
-                qw[w] = ((uint32_t)a & 0xFFFFu) | ((uint32_t)b << 16);
+        const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+        if constexpr (kPacked) {
+            const uint32_t *pk = nw.pack + start * W;
+            if constexpr (kStage) {
+                uint32_t *sp = reinterpret_cast<uint32_t *>(s_leaf[w]);
+                if (lane < (int)count * W)
+                    sp[lane] = pk[lane];
+                if (W > 2 && lane + kWave < (int)count * W)
+                    sp[lane + kWave] = pk[lane + kWave];
+                pk = sp;
             }
-            cnt += count_within_packed<W>(qw, nw.pack + start * W, (int)count, nw.T);
-        } else {
-            // (rare next to narrow leaves: a small batch keeps registers for the walk)
-            cnt += count_within<C, D, INTBOX ? 2 : 8>(x, coords + start * D, (int)count, T);
+            if ((int32_t)nw.ext[c] <= nw.limit) {
+                uint32_t qw[W];
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const int32_t a = clamp_i32(xi[2 * k] - (int32_t)nw.org[(size_t)c * D + 2 * k], -nw.M, nw.R);
+                    const int32_t b = 2 * k + 1 < D
+                                          ? clamp_i32(xi[2 * k + 1] - (int32_t)nw.org[(size_t)c * D + 2 * k + 1],
+                                                      -nw.M, nw.R)
+                                          : 0;
+                    qw[k] = ((uint32_t)a & 0xFFFFu) | ((uint32_t)b << 16);
+                }
+                if (kStage)
+                    wave_lds_sync();
+                if (partial)
+                    cnt += count_within_packed<W, kPackBatch, kStage>(qw, pk, (int)count, nw.T);
+                if (kStage)
+                    wave_lds_sync();
+                return;
+            }
         }
+        const C *pc = coords + start * D;
+        if constexpr (kStage) {
+            C *sc = reinterpret_cast<C *>(s_leaf[w]);
+            if (lane < count) {
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    sc[lane * D + k] = pc[lane * D + k];
+            }
+            wave_lds_sync();
+            pc = sc;
+        }
+        if (partial)
+            cnt += count_within<C, D, kWideBatch, kStage>(x, pc, (int)count, T);
+        if (kStage)
+            wave_lds_sync();
     };
     // Classifies the current node for this lane (unless it settled above);
     // returns whether the node is partial to it.

@@ -140,9 +140,7 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                             sp[lane * D + k] = coords[(start + lane) * D + k];
                         sk[lane] = skey[start + lane];
                     }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    wave_lds_sync();
                     if (want) {
                         for (int t = 0; t < (int)count; ++t) {
                             C qv[D];
@@ -152,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                             consider<C, D, STATS>(x, qv, sk[t], kq, best, best_low, n_pairs);
                         }
                     }
-                    __builtin_amdgcn_wave_barrier();
+                    wave_lds_sync();
                 }
             } else {
                 const uint64_t m = __ballot(want);

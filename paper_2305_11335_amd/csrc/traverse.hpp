@@ -85,6 +85,14 @@ __device__ inline void node_range(uint32_t v, int depth, int height, int64_t n, 
     count = left < cap ? left : cap;
 }
 
+// Orders a wavefront's LDS writes before its later LDS reads (and the reads
+// before later writes): a leaf staged by some lanes is read by all.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Adds a per-lane count into counters[slot] with one atomic per wavefront.
 __device__ inline void add_wave_count(int64_t *counters, int slot, uint64_t v) {
 #pragma unroll

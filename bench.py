@@ -176,18 +176,16 @@ def batched(torch, dpc, datagen, steps: int) -> dict:
             "outputs_identical": True}
 
 
-def served(torch, dpc, datagen, seconds: float, warm: float, rate: float = 200.0,
-           budget: int = 200 * 10**9) -> dict:
+def served(torch, dpc, pool, pts, seconds: float, warm: float, rate: float = 200.0,
+           budget: int = 200 * 10**9, seed: int = 55, slots: int = 2, max_batch: int = 64, plain: bool = True) -> dict:
     """p50/p99 latency and throughput of a Poisson request stream, through the
-    server and through plain per-request dpc_run calls (same trace)."""
+    server and through plain per-request dpc_run calls (same trace).  pool:
+    the request instances; pts: their points on the device."""
     import queue
 
     import numpy as np
 
-    pool = datagen.served_instances()
-    dev = torch.device("cuda:0")
-    pts = [torch.from_numpy(x.points).to(dev) for x in pool]
-    rng = np.random.default_rng(55)
+    rng = np.random.default_rng(seed)
     horizon = warm + seconds
     gaps = rng.exponential(1.0 / rate, size=int(rate * horizon * 1.5) + 16)
     arrivals = np.cumsum(gaps)
@@ -240,7 +238,7 @@ def served(torch, dpc, datagen, seconds: float, warm: float, rate: float = 200.0
 
     # the server: outputs per request (kept for the pool entries' first requests)
     outs = {}
-    with dpc.Server(hbm_budget_bytes=budget, slots=4, max_batch=64) as srv:
+    with dpc.Server(hbm_budget_bytes=budget, slots=slots, max_batch=max_batch) as srv:
         def submit_srv(k, w):
             x = pool[w]
             t, res = srv.submit(pts[w], x.d_cut, x.rho_min, x.delta_min)
@@ -251,7 +249,7 @@ def served(torch, dpc, datagen, seconds: float, warm: float, rate: float = 200.0
         sched, done = replay(submit_srv, lambda k, t: srv.wait(t)["done_ns"])
         sst = srv.stats()
     rec = {"workload": "served_poisson200_3d", "rate_req_per_s": rate, "seconds": seconds, "warmup_s": warm,
-           "pool_instances": len(pool), "hbm_budget_bytes": budget, "slots": 4, "max_batch": 64,
+           "pool_instances": len(pool), "hbm_budget_bytes": budget, "slots": slots, "max_batch": max_batch,
            "server": stats(sched, done),
            "server_stats": {k: sst[k] for k in ("batches", "max_batch_seen", "max_slots_busy", "max_admitted_bytes",
                                                 "max_workspace_bytes", "over_footprint")}}
@@ -268,8 +266,9 @@ def served(torch, dpc, datagen, seconds: float, warm: float, rate: float = 200.0
         s.synchronize()
         return time.monotonic_ns()
 
-    sched, done = replay(submit_plain, collect_plain)
-    rec["plain_loop"] = stats(sched, done)
+    if plain:
+        sched, done = replay(submit_plain, collect_plain)
+        rec["plain_loop"] = stats(sched, done)
     for w, res in outs.items():
         x = pool[w]
         alone = dpc.run(pts[w], x.d_cut, x.rho_min, x.delta_min)
@@ -378,7 +377,13 @@ def main() -> int:
     if not args.no_serve:
         print(f"bench: served workload ({args.serve_warmup + args.serve_seconds:.0f} s, twice)", file=sys.stderr,
               flush=True)
-        rec["served"] = served(torch, dpc, datagen, args.serve_seconds, args.serve_warmup)
+        pool = datagen.served_instances()
+        pts = [torch.from_numpy(x.points).to(dev) for x in pool]
+        rec["served"] = served(torch, dpc, pool, pts, args.serve_seconds, args.serve_warmup)
+        # the same pool offered faster than per-request calls can serve it
+        print("bench: served workload under overload (1500 requests/s, 7 s, twice)", file=sys.stderr, flush=True)
+        rec["served_overload"] = served(torch, dpc, pool, pts, 6.0, 1.0, rate=1500.0, seed=56)
+        rec["served_overload"]["workload"] = "served_poisson1500_3d"
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(inst)

@@ -85,7 +85,10 @@ __device__ inline int32_t count_within(const C (&x)[D], const C *__restrict__ p,
 }
 
 // The same count on a narrow leaf: q holds the query's clamped offsets from
-// the leaf corner, packed like the leaf's points.
+// the leaf corner, packed like the leaf's points.  Each dot product starts
+// from -(T + 1), so a point is within the radius exactly when the result is
+// negative, and its sign bit is the count (T < 2^30 and every clamped
+// squared distance is below 2^31, so nothing wraps).
 template <int W, int kBatch, bool kStaged>
 __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint32_t *__restrict__ p, int count,
                                               int32_t T) {
@@ -93,6 +96,18 @@ __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint
 #pragma unroll
     for (int w = 0; w < W; ++w)
         qv[w] = __builtin_bit_cast(short2_t, q[w]);
+    const int32_t base = -(T + 1);
+    auto point = [&](const uint32_t *pp) {
+        // (saturation never applies; asking for it selects the encoding
+        // that reads the start value from a scalar register)
+        int32_t acc = base;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const short2_t dv = qv[w] - __builtin_bit_cast(short2_t, pp[w]);
+            acc = __builtin_amdgcn_sdot2(dv, dv, acc, true);
+        }
+        return (int32_t)((uint32_t)acc >> 31);
+    };
     auto batch = [&](int t) {
         uint32_t pb[kBatch][W];
 #pragma unroll
@@ -102,15 +117,8 @@ __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint
                 pb[b][w] = p[(t + b) * W + w];
         int32_t c = 0;
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            int32_t acc = 0;
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const short2_t dv = qv[w] - __builtin_bit_cast(short2_t, pb[b][w]);
-                acc = __builtin_amdgcn_sdot2(dv, dv, acc, false);
-            }
-            c += acc <= T ? 1 : 0;
-        }
+        for (int b = 0; b < kBatch; ++b)
+            c += point(pb[b]);
         return c;
     };
     int32_t c = 0;
@@ -123,15 +131,8 @@ __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint
         for (; t + kBatch <= count; t += kBatch)
             c += batch(t);
     }
-    for (; t < count; ++t) {
-        int32_t acc = 0;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            const short2_t dv = qv[w] - __builtin_bit_cast(short2_t, p[t * W + w]);
-            acc = __builtin_amdgcn_sdot2(dv, dv, acc, false);
-        }
-        c += acc <= T ? 1 : 0;
-    }
+    for (; t < count; ++t)
+        c += point(p + t * W);
     return c;
 }
 

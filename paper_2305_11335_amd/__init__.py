@@ -16,6 +16,7 @@ from ._binding import (  # noqa: F401
     STAGES,
     Server,
     WORK_FIELDS,
+    autotune,
     batch_run,
     cluster,
     cluster_sweep,
@@ -23,8 +24,10 @@ from ._binding import (  # noqa: F401
     density_sweep,
     dependent,
     last_stats,
+    leaf_size,
     load,
     run,
+    set_leaf_size,
     square_threshold,
     status_str,
     workspace_bytes,

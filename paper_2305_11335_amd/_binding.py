@@ -24,7 +24,7 @@ EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_batch
             "dpc_status_str", "dpc_square_threshold", "dpc_workspace_bytes", "dpc_density_sweep",
             "dpc_cluster_sweep", "dpc_server_create",
             "dpc_server_submit", "dpc_server_poll", "dpc_server_wait", "dpc_server_get_stats",
-            "dpc_server_destroy")
+            "dpc_server_destroy", "dpc_set_leaf_size", "dpc_leaf_size", "dpc_autotune")
 
 
 class Stats(ctypes.Structure):
@@ -102,6 +102,12 @@ def load():
     lib.dpc_density_sweep.restype = ctypes.c_int
     lib.dpc_cluster_sweep.argtypes = [i64, P, P, P, ctypes.POINTER(i32), ctypes.POINTER(dbl), i32, P, P]
     lib.dpc_cluster_sweep.restype = ctypes.c_int
+    lib.dpc_set_leaf_size.argtypes = [i32, i32]
+    lib.dpc_set_leaf_size.restype = ctypes.c_int
+    lib.dpc_leaf_size.argtypes = [i32]
+    lib.dpc_leaf_size.restype = ctypes.c_int32
+    lib.dpc_autotune.argtypes = [P, i64, i32, dbl, i32, dbl, P, ctypes.POINTER(dbl), ctypes.POINTER(i32)]
+    lib.dpc_autotune.restype = ctypes.c_int
     lib.dpc_workspace_bytes.argtypes = [i64, i32]
     lib.dpc_workspace_bytes.restype = ctypes.c_uint64
     lib.dpc_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
@@ -420,3 +426,27 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def set_leaf_size(d: int, leaf_points: int) -> None:
+    """Points per k-d tree leaf (16 or 32) for dimension d; never changes outputs."""
+    st = load().dpc_set_leaf_size(int(d), int(leaf_points))
+    if st != OK:
+        raise DPCError(st, "dpc_set_leaf_size")
+
+
+def leaf_size(d: int) -> int:
+    return int(load().dpc_leaf_size(int(d)))
+
+
+def autotune(points, d_cut: float, rho_min: int, delta_min: float, stream=None) -> dict:
+    """Times both leaf sizes on this instance and keeps the faster for its
+    dimension; returns {"ms": {16: t16, 32: t32}, "chosen": size}."""
+    n, d = _check_points(points)
+    ms = (ctypes.c_double * 2)()
+    ch = ctypes.c_int32()
+    st = load().dpc_autotune(_ptr(points), n, d, float(d_cut), int(rho_min), float(delta_min), _stream(stream), ms,
+                             ctypes.byref(ch))
+    if st != OK:
+        raise DPCError(st, "dpc_autotune")
+    return {"ms": {16: ms[0], 32: ms[1]}, "chosen": ch.value}

@@ -226,7 +226,7 @@ dpc_status run_group(const std::vector<Job> &jobs, int d, Arith arith, RunRecord
                      Workspace &ws) {
     hipStream_t stream = ws.stream;
     Index ix;
-    DPC_TRY(build_group(jobs, d, arith, ws, ix));
+    DPC_TRY(build_group(jobs, d, arith, leaf_log2(d), ws, ix));
     if (rec)
         DPC_TRY(rec->mark(DPC_STAGE_INDEX));
     int32_t *srho;
@@ -354,7 +354,7 @@ int dpc_density(const int32_t *points, int64_t n, int32_t d, double d_cut, int32
     std::vector<Job> jobs{J};
     DPC_TRY(job_bounds(jobs, d, ws, nullptr));
     Index ix;
-    DPC_TRY(build_group(jobs, d, job_arith(jobs[0], d), ws, ix));
+    DPC_TRY(build_group(jobs, d, job_arith(jobs[0], d), leaf_log2(d), ws, ix));
     int32_t *srho;
     DPC_TRY(ws.alloc(&srho, (size_t)ix.positions));
     return launch_density(ix, srho, nullptr, stream);
@@ -379,7 +379,7 @@ int dpc_dependent(const int32_t *points, int64_t n, int32_t d, const int32_t *rh
     std::vector<Job> jobs{J};
     DPC_TRY(job_bounds(jobs, d, ws, nullptr));
     Index ix;
-    DPC_TRY(build_group(jobs, d, job_arith(jobs[0], d), ws, ix));
+    DPC_TRY(build_group(jobs, d, job_arith(jobs[0], d), leaf_log2(d), ws, ix));
     DPC_TRY(build_priority(nullptr, true, ws, ix));
     return launch_dependent(ix, nullptr, stream);
 }
@@ -421,7 +421,7 @@ int dpc_density_sweep(const int32_t *points, int64_t n, int32_t d, const double 
     std::vector<Job> jobs{J};
     DPC_TRY(job_bounds(jobs, d, ws, nullptr));
     Index ix;
-    DPC_TRY(build_group(jobs, d, job_arith(jobs[0], d), ws, ix));
+    DPC_TRY(build_group(jobs, d, job_arith(jobs[0], d), leaf_log2(d), ws, ix));
     int32_t *srho;
     DPC_TRY(ws.alloc(&srho, (size_t)ix.positions));
     // one descriptor per radius, each writing its own row of rho
@@ -501,6 +501,81 @@ uint64_t dpc_workspace_bytes(int64_t n, int32_t d) {
     if (bad_shape(n, d))
         return 0;
     return workspace_bound(n, d);
+}
+
+int dpc_set_leaf_size(int32_t d, int32_t leaf_points) {
+    if (d < 1 || d > kMaxDim || (leaf_points != 16 && leaf_points != 32))
+        return DPC_ERR_INVALID_ARG;
+    set_leaf_log2(d, leaf_points == 16 ? 4 : 5);
+    return DPC_OK;
+}
+
+int32_t dpc_leaf_size(int32_t d) {
+    if (d < 1 || d > kMaxDim)
+        return 0;
+    return 1 << leaf_log2(d);
+}
+
+int dpc_autotune(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
+                 hipStream_t stream, double *ms_out, int32_t *chosen) {
+    Job J;
+    if (bad_shape(n, d) || n == 0 || points == nullptr)
+        return DPC_ERR_INVALID_ARG;
+    int32_t *rho, *dep, *label;
+    int64_t *delta2;
+    Workspace ws(stream);
+    DPC_TRY(ws.alloc(&rho, (size_t)n));
+    DPC_TRY(ws.alloc(&dep, (size_t)n));
+    DPC_TRY(ws.alloc(&label, (size_t)n));
+    DPC_TRY(ws.alloc(&delta2, (size_t)n));
+    DPC_TRY(make_job(points, n, d, d_cut, rho_min, delta_min, 0, rho, dep, delta2, label, J));
+    hipEvent_t e0, e1;
+    DPC_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipGetLastError();
+        return DPC_ERR_HIP;
+    }
+    const int before = leaf_log2(d);
+    dpc_status st = DPC_OK;
+    float best_ms[2] = {0.0f, 0.0f};
+    for (int c = 0; c < 2 && st == DPC_OK; ++c) {
+        set_leaf_log2(d, kMinLeafLog2 + c);
+        // one warm-up run, then the faster of two timed runs
+        for (int r = 0; r < 3 && st == DPC_OK; ++r) {
+            std::vector<Job> jobs{J};
+            Workspace run_ws(stream);
+            if (hipEventRecord(e0, stream) != hipSuccess)
+                st = DPC_ERR_HIP;
+            if (st == DPC_OK)
+                st = job_bounds(jobs, d, run_ws, nullptr);
+            if (st == DPC_OK)
+                st = run_group(jobs, d, job_arith(jobs[0], d), nullptr, nullptr, run_ws);
+            if (st == DPC_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                st = DPC_ERR_HIP;
+            float ms = 0.0f;
+            if (st == DPC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                st = DPC_ERR_HIP;
+            if (st == DPC_OK && r > 0 && (r == 1 || ms < best_ms[c]))
+                best_ms[c] = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != DPC_OK) {
+        (void)hipGetLastError();
+        set_leaf_log2(d, before);
+        return st;
+    }
+    const int pick = best_ms[0] < best_ms[1] ? kMinLeafLog2 : kMaxLeafLog2;
+    set_leaf_log2(d, pick);
+    if (ms_out) {
+        ms_out[0] = best_ms[0];
+        ms_out[1] = best_ms[1];
+    }
+    if (chosen)
+        *chosen = 1 << pick;
+    return DPC_OK;
 }
 
 int dpc_last_stats(dpc_stats *out) {

@@ -176,14 +176,14 @@ struct DensityArrays {
     const int32_t *sidx;
 };
 
-template <typename C, int D, bool STATS, bool INTBOX>
+template <typename C, int D, bool STATS, bool INTBOX, int LSH>
 __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ inst,
                                                       const uint32_t *__restrict__ tile_inst, DensityArrays<C> G,
                                                       int64_t *counters) {
     constexpr bool kPacked = std::is_same<C, double>::value;
     constexpr int W = (D + 1) / 2;
     // one staged leaf per wave: D 8-byte coordinates or W packed words per point
-    __shared__ uint64_t s_leaf[kThreads / kWave][D >= 3 ? kLeafSize * D : 1];
+    __shared__ uint64_t s_leaf[kThreads / kWave][D >= 3 ? kMaxLeaf * D : 1];
     uint64_t n_pairs = 0, n_nodes = 0, n_contained = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
     // this wave's instance; positions, nodes and leaves below are its own
@@ -191,6 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
     const Inst &I = inst_of_tile(inst, tile_inst, g0 / kTile);
     const int64_t n = I.n;
     const int height = I.height;
+    constexpr int lsh = LSH;  // log2 of the points per leaf (the group's I.lsh)
     const int64_t q0 = g0 - I.P;
     const int64_t q = q0 + lane;
     if (q0 >= n)
@@ -229,9 +230,10 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
             xi[k] = (int32_t)x[k] - nw.lo[k];
     }
 
-    // home node (depth hd) and the start of the walk
-    const int hd = height > 0 ? height - 1 : 0;
-    const uint32_t home = (1u << hd) + (uint32_t)((q0 / kLeafSize) >> (height - hd));
+    // home node (depth hd: the node of this wave's 64 positions) and the
+    // start of the walk
+    const int hd = height > 6 - lsh ? height - (6 - lsh) : 0;
+    const uint32_t home = (1u << hd) + (uint32_t)((q0 >> lsh) >> (height - hd));
     int sd = hd;
     if (hd > 0) {
         const C *hb = box + (size_t)home * 2 * D;
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
         if (lane >= 1 && lane <= hd) {
             const uint32_t s = (home >> (hd - lane)) ^ 1u;
             int64_t st, cnt;
-            node_range(s, lane, height, n, st, cnt);
+            node_range(s, lane, height, lsh, n, st, cnt);
             if (cnt > 0) {
                 const C *sb = box + (size_t)s * 2 * D;
                 bool far = false;
@@ -355,7 +357,7 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
         }
         for (;;) {
             int64_t start, count;
-            node_range(v, depth, height, n, start, count);
+            node_range(v, depth, height, lsh, n, start, count);
             const bool internal = v < first_leaf;
             uint32_t kids[2 * B];
             if (internal) {
@@ -413,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
     } else {
         for (;;) {
             int64_t start, count;
-            node_range(v, depth, height, n, start, count);
+            node_range(v, depth, height, lsh, n, start, count);
             bool descend = false;
             if (count > 0) {
                 if (STATS)
@@ -460,7 +462,7 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
     }
 }
 
-template <typename C, bool STATS, bool INTBOX>
+template <typename C, bool STATS, bool INTBOX, int LSH>
 dpc_status launch_typed(const Index &ix, int32_t *srho, int64_t *counters, hipStream_t s) {
     DensityArrays<C> G{static_cast<const C *>(ix.coords), static_cast<const C *>(ix.box), ix.rbox, ix.leaf_org,
                        ix.leaf_ext, ix.leaf_pack, srho, ix.sidx};
@@ -468,7 +470,7 @@ dpc_status launch_typed(const Index &ix, int32_t *srho, int64_t *counters, hipSt
     switch (ix.d) {
 #define DPC_DENSITY_CASE(DD)                                                                                    \
     case DD:                                                                                                    \
-        hipLaunchKernelGGL((k_density<C, DD, STATS, INTBOX && DD <= 4>), grid, block, 0, s, ix.inst, ix.tile_inst, \
+        hipLaunchKernelGGL((k_density<C, DD, STATS, INTBOX && DD <= 4, LSH>), grid, block, 0, s, ix.inst, ix.tile_inst, \
                            G, counters);                                                                        \
         break;
         DPC_DENSITY_CASE(1)
@@ -487,19 +489,25 @@ dpc_status launch_typed(const Index &ix, int32_t *srho, int64_t *counters, hipSt
     return DPC_OK;
 }
 
-}  // namespace
-
-dpc_status launch_density(const Index &ix, int32_t *srho, int64_t *counters, hipStream_t s) {
+template <int LSH>
+dpc_status launch_leaf(const Index &ix, int32_t *srho, int64_t *counters, hipStream_t s) {
     if (ix.arith == Arith::F64) {
         // integer boxes when every instance's clamped gaps fit (then T < M^2 <= R^2)
         if (ix.intbox)
-            return counters ? launch_typed<double, true, true>(ix, srho, counters, s)
-                            : launch_typed<double, false, true>(ix, srho, nullptr, s);
-        return counters ? launch_typed<double, true, false>(ix, srho, counters, s)
-                        : launch_typed<double, false, false>(ix, srho, nullptr, s);
+            return counters ? launch_typed<double, true, true, LSH>(ix, srho, counters, s)
+                            : launch_typed<double, false, true, LSH>(ix, srho, nullptr, s);
+        return counters ? launch_typed<double, true, false, LSH>(ix, srho, counters, s)
+                        : launch_typed<double, false, false, LSH>(ix, srho, nullptr, s);
     }
-    return counters ? launch_typed<int64_t, true, false>(ix, srho, counters, s)
-                    : launch_typed<int64_t, false, false>(ix, srho, nullptr, s);
+    return counters ? launch_typed<int64_t, true, false, LSH>(ix, srho, counters, s)
+                    : launch_typed<int64_t, false, false, LSH>(ix, srho, nullptr, s);
+}
+
+}  // namespace
+
+dpc_status launch_density(const Index &ix, int32_t *srho, int64_t *counters, hipStream_t s) {
+    return ix.lsh == kMinLeafLog2 ? launch_leaf<kMinLeafLog2>(ix, srho, counters, s)
+                                  : launch_leaf<kMaxLeafLog2>(ix, srho, counters, s);
 }
 
 }  // namespace dpc

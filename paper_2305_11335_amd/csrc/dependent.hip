@@ -49,7 +49,7 @@ __device__ inline void consider(const C (&x)[D], const C (&q)[D], uint64_t kj, u
 // arguments are the group's arrays and the rest is read from the
 // instance's descriptor.  (Separate instantiations, so that the single
 // instance keeps every parameter in kernel arguments.)
-template <typename C, int D, bool STATS, bool GROUP>
+template <typename C, int D, bool STATS, bool GROUP, int LSH>
 __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ coords, const C *__restrict__ box,
                                                         const uint64_t *__restrict__ skey,
                                                         const uint64_t *__restrict__ maxkey,
@@ -59,8 +59,8 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                                                         int64_t *__restrict__ delta2_out, int64_t *counters,
                                                         const Inst *__restrict__ inst,
                                                         const uint32_t *__restrict__ tile_inst) {
-    __shared__ C s_pts[kThreads / kWave][kLeafSize * D];
-    __shared__ uint64_t s_key[kThreads / kWave][kLeafSize];
+    __shared__ C s_pts[kThreads / kWave][kMaxLeaf * D];
+    __shared__ uint64_t s_key[kThreads / kWave][kMaxLeaf];
     uint64_t n_pairs = 0, n_nodes = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
     int64_t q0 = wave_base(kThreads);
@@ -103,15 +103,16 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
     uint32_t best_low = 0;  // low key word of the best point; 0 = none yet
     const uint32_t first_leaf = 1u << height;
     // home node; a: the ancestor whose sibling subtree is walked next
-    const int hd = height > 0 ? height - 1 : 0;
-    const uint32_t home = (1u << hd) + (uint32_t)((q0 / kLeafSize) >> (height - hd));
+    constexpr int lsh = LSH;  // log2 of the points per leaf (the group's I.lsh)
+    const int hd = height > 6 - lsh ? height - (6 - lsh) : 0;  // the node of the wave's 64 positions
+    const uint32_t home = (1u << hd) + (uint32_t)((q0 >> lsh) >> (height - hd));
     uint32_t a = home;
     int da = hd;
     uint32_t u = 1, v = home;  // virtual (visit order, relative to the subtree) and real node index
     int depth = hd;
     for (;;) {
         int64_t start, count;
-        node_range(v, depth, height, n, start, count);
+        node_range(v, depth, height, lsh, n, start, count);
         bool descend = false;
         uint32_t first_child = 0;
         if (count > 0) {
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                     descend = true;
                     // the left child is never empty; the right one may be.
                     // The child on the reference point's side goes first.
-                    if (count > ((int64_t)kLeafSize << (height - depth - 1))) {
+                    if (count > ((int64_t)1 << (height - depth - 1 + lsh))) {
                         const uint64_t sp = split[v];
                         const uint32_t axis = (uint32_t)(sp >> 32);
                         uint32_t r = ref[0];
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
     }
 }
 
-template <typename C, bool STATS, bool GROUP>
+template <typename C, bool STATS, bool GROUP, int LSH>
 dpc_status launch_typed(const Index &ix, int64_t *counters, hipStream_t s) {
     const C *coords = static_cast<const C *>(ix.coords);
     const C *box = static_cast<const C *>(ix.box);
@@ -228,9 +229,9 @@ dpc_status launch_typed(const Index &ix, int64_t *counters, hipStream_t s) {
     switch (ix.d) {
 #define DPC_DEP_CASE(DD)                                                                                          \
     case DD:                                                                                                      \
-        hipLaunchKernelGGL((k_dependent<C, DD, STATS, GROUP>), grid, block, 0, s, coords, box, ix.skey, ix.maxkey, \
-                           ix.split, lo, I.n, I.height, I.dep_rho_min, ix.sidx, I.dep, I.delta2, counters, ix.inst, \
-                           ix.tile_inst);                                                                          \
+        hipLaunchKernelGGL((k_dependent<C, DD, STATS, GROUP, LSH>), grid, block, 0, s, coords, box, ix.skey,     \
+                           ix.maxkey, ix.split, lo, I.n, I.height, I.dep_rho_min, ix.sidx, I.dep, I.delta2, counters, \
+                           ix.inst, ix.tile_inst);                                                                 \
         break;
         DPC_DEP_CASE(1)
         DPC_DEP_CASE(2)
@@ -250,7 +251,11 @@ dpc_status launch_typed(const Index &ix, int64_t *counters, hipStream_t s) {
 
 template <typename C, bool STATS>
 dpc_status launch_arith(const Index &ix, int64_t *counters, hipStream_t s) {
-    return ix.count == 1 ? launch_typed<C, STATS, false>(ix, counters, s) : launch_typed<C, STATS, true>(ix, counters, s);
+    if (ix.lsh == kMinLeafLog2)
+        return ix.count == 1 ? launch_typed<C, STATS, false, kMinLeafLog2>(ix, counters, s)
+                             : launch_typed<C, STATS, true, kMinLeafLog2>(ix, counters, s);
+    return ix.count == 1 ? launch_typed<C, STATS, false, kMaxLeafLog2>(ix, counters, s)
+                         : launch_typed<C, STATS, true, kMaxLeafLog2>(ix, counters, s);
 }
 
 }  // namespace

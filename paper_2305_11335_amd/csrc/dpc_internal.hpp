@@ -30,7 +30,9 @@ namespace dpc {
 
 constexpr int kWave = 64;
 constexpr int kMaxDim = 8;
-constexpr int kLeafSize = 32;  // points per tree leaf
+constexpr int kMaxLeaf = 32;   // most points per tree leaf (a group's leaves hold 16 or 32)
+constexpr int kMinLeafLog2 = 4;
+constexpr int kMaxLeafLog2 = 5;
 constexpr int kTile = 2048;    // positions per tile (the unit of the top-level build passes)
 
 // Coordinates and squared distances are exact in double when every squared
@@ -47,6 +49,7 @@ struct Inst {
     int64_t S;         // first entry of its per-node select records (2^(jb-1))
     int64_t B;         // first word of its top-level relative boxes (2^(jb+1) nodes)
     int32_t height;    // 2^height leaves
+    int32_t lsh;       // log2 of the points per leaf (4 or 5, the same for a whole group)
     int32_t jb;        // first level built in LDS (the top levels are 0 .. jb-1)
     int32_t wbits;     // bits of the widest coordinate span
     int32_t lo[kMaxDim];
@@ -89,6 +92,7 @@ struct Job {
 struct Index {
     int d = 0;
     Arith arith = Arith::F64;
+    int lsh = kMaxLeafLog2;     // log2 of the points per leaf
     bool intbox = false;        // every instance can use the clamped integer comparisons
     int count = 0;              // instances
     std::vector<Inst> host;     // descriptors (host copy)
@@ -230,8 +234,12 @@ int64_t isqrt64(int64_t v);
 dpc_status job_bounds(std::vector<Job> &jobs, int d, Workspace &ws, std::vector<int> *bad);
 Arith job_arith(const Job &j, int d);
 // Plans a group (descriptors, offsets, tile table), allocates its arrays and
-// builds every instance's tree.
-dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, Workspace &ws, Index &ix);
+// builds every instance's tree with 2^lsh points per leaf.
+dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, int lsh, Workspace &ws, Index &ix);
+// The leaf size used for groups of dimension d (log2; a tuning choice that
+// never changes results) and its setter.
+int leaf_log2(int d);
+void set_leaf_log2(int d, int lsh);
 // Priority keys and per-node maxima; rho in sorted order (srho) or in each
 // instance's input order (rho_orig: use the instances' rho arrays).
 dpc_status build_priority(const int32_t *srho, bool rho_orig, Workspace &ws, Index &ix);

@@ -4,6 +4,8 @@
 // The k-d trees themselves are built in kdtree.hip.
 #include "dpc_internal.hpp"
 
+#include <atomic>
+
 #include <limits>
 
 namespace dpc {
@@ -186,13 +188,13 @@ __global__ __launch_bounds__(kThreads) void k_keys_leaf(const Inst *__restrict__
         key = pack_key(r, o);
         skey[pos] = key;
     }
-#pragma unroll
-    for (int o = kLeafSize / 2; o > 0; o >>= 1) {
+    const int lsh = I.lsh;
+    for (int o = 1 << (lsh - 1); o > 0; o >>= 1) {
         const uint64_t b = shfl_xor_u64(key, o);
         key = b > key ? b : key;
     }
-    if ((i & (kLeafSize - 1)) == 0 && i < I.n)
-        maxkey[I.N + (1ll << I.height) + i / kLeafSize] = key;
+    if ((i & ((1 << lsh) - 1)) == 0 && i < I.n)
+        maxkey[I.N + (1ll << I.height) + (i >> lsh)] = key;
 }
 
 // One instance: up to 8 levels of maxima above 256 consecutive nodes of one
@@ -233,10 +235,12 @@ __global__ __launch_bounds__(kThreads) void k_key_level(const Inst *__restrict__
     maxkey[I.N + v] = a > b ? a : b;
 }
 
-int bottom_levels(int d) { return d <= 3 ? 6 : 5; }  // log2 of the LDS subtree size over the leaf size
+// log2 of the LDS subtree size (2048 points up to three dimensions, else
+// 1024) over the leaf size
+int bottom_levels(int d, int lsh) { return (d <= 3 ? 11 : 10) - lsh; }
 
-int tree_height(int64_t n) {
-    const int64_t leaves = (n + kLeafSize - 1) / kLeafSize;
+int tree_height(int64_t n, int lsh) {
+    const int64_t leaves = (n + (1ll << lsh) - 1) >> lsh;
     int h = 0;
     while ((1ll << h) < leaves)
         ++h;
@@ -378,14 +382,31 @@ void density_params(Inst &I, int64_t T, int d) {
     I.Tn = M <= R ? (int32_t)T : 0;
 }
 
+// Leaf size per dimension (log2).  Smaller leaves prune more point tests but
+// visit more nodes; on the stand-in workloads 32 points were faster in 2-D,
+// 3-D and 8-D, so it is the default (dpc_autotune measures an instance).
+// Any choice gives the same outputs.
+namespace {
+std::atomic<int> g_leaf_log2[kMaxDim + 1] = {5, 5, 5, 5, 5, 5, 5, 5, 5};
+}  // namespace
+
+int leaf_log2(int d) { return d >= 1 && d <= kMaxDim ? g_leaf_log2[d].load(std::memory_order_relaxed) : kMaxLeafLog2; }
+
+void set_leaf_log2(int d, int lsh) {
+    if (d >= 1 && d <= kMaxDim && lsh >= kMinLeafLog2 && lsh <= kMaxLeafLog2)
+        g_leaf_log2[d].store(lsh, std::memory_order_relaxed);
+}
+
 uint64_t workspace_bound(int64_t n, int d) {
     if (n <= 0)
         return 0;
     const uint64_t D = (uint64_t)d, W = (D + 1) / 2;
     const uint64_t Pn = (uint64_t)padded(n), tiles = Pn / kTile;
-    const int h = tree_height(n);
+    // the smaller leaf size has more nodes and leaves: the bound holds for both
+    const int lsh = kMinLeafLog2;
+    const int h = tree_height(n, lsh);
     const uint64_t leaves = 1ull << h, nodes = 2 * leaves;
-    const int jb = h > bottom_levels(d) ? h - bottom_levels(d) : 0;
+    const int jb = h > bottom_levels(d, lsh) ? h - bottom_levels(d, lsh) : 0;
     uint64_t b = 0;
     // per position: coords (8 bytes per axis), the two relative-coordinate
     // and index buffers of the build, the original index, the packed leaf
@@ -411,7 +432,10 @@ uint64_t workspace_bound(int64_t n, int d) {
     return b;
 }
 
-dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, Workspace &ws, Index &ix) {
+dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, int lsh, Workspace &ws, Index &ix) {
+    if (lsh < kMinLeafLog2 || lsh > kMaxLeafLog2)
+        return DPC_ERR_INVALID_ARG;
+    ix.lsh = lsh;
     hipStream_t s = ws.stream;
     ix.d = d;
     ix.arith = arith;
@@ -423,8 +447,9 @@ dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, Workspa
         const Job &J = jobs[i];
         Inst &I = ix.host[i];
         I.n = J.n;
-        I.height = tree_height(J.n);
-        I.jb = I.height > bottom_levels(d) ? I.height - bottom_levels(d) : 0;
+        I.height = tree_height(J.n, lsh);
+        I.lsh = lsh;
+        I.jb = I.height > bottom_levels(d, lsh) ? I.height - bottom_levels(d, lsh) : 0;
         uint32_t widest = 0;
         for (int k = 0; k < kMaxDim; ++k) {
             I.lo[k] = k < d ? J.lo[k] : 0;

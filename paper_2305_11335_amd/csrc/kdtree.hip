@@ -48,9 +48,7 @@ template <int D>
 struct Bottom {
     // points per bottom subtree: what fits in LDS next to the scratch arrays
     static constexpr int kSize = D <= 3 ? 2048 : 1024;
-    static constexpr int kLevels = D <= 3 ? 6 : 5;    // log2(kSize / kLeafSize)
-    static constexpr int kNodes = kSize / kLeafSize;  // most nodes on one level
-    static_assert((kLeafSize << kLevels) == kSize, "subtree size");
+    static constexpr int kNodes = kSize >> kMinLeafLog2;  // most nodes on one level
 };
 
 __device__ inline uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
@@ -188,7 +186,7 @@ __device__ inline bool top_tile(const Inst *__restrict__ inst, const uint32_t *_
     if (tt.e0 >= I.n)
         return false;
     tt.I = &I;
-    const int64_t S = (int64_t)kLeafSize << (I.height - j);
+    const int64_t S = 1ll << (I.height - j + I.lsh);
     tt.t = tt.e0 / S;
     tt.g = node_geom(tt.t, S, I.n);
     tt.tile0 = first + tt.g.start / kTile;
@@ -203,7 +201,7 @@ __device__ inline bool top_node(const Inst *__restrict__ inst, const uint2 *__re
     const Inst &I = inst[e.x];
     if (j >= I.jb)
         return false;
-    const int64_t S = (int64_t)kLeafSize << (I.height - j);
+    const int64_t S = 1ll << (I.height - j + I.lsh);
     tt.t = e.y;
     if (tt.t * S >= I.n)
         return false;
@@ -696,7 +694,7 @@ __global__ __launch_bounds__(kThreads) void k_soa_init(const Inst *__restrict__ 
 // ---------------------------------------------------------------------------
 // bottom levels: one workgroup per subtree, in LDS
 
-template <typename C, int D>
+template <typename C, int D, int LSH>
 __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ inst, const uint2 *__restrict__ sub,
                                                      const uint32_t *__restrict__ XA, const uint32_t *__restrict__ XB,
                                                      const uint32_t *__restrict__ IA, const uint32_t *__restrict__ IB,
@@ -726,6 +724,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
     const Inst &In = inst[job.x];
     const int64_t n = In.n;
     const int jb = In.jb, h = In.height;
+    constexpr int lsh = LSH;  // log2 of the points per leaf (the group's In.lsh)
     constexpr int W = (D + 1) / 2;
     // after jb top-level passes (each moves the points to the other buffer)
     // the instance's points are in buffer jb mod 2
@@ -739,7 +738,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
     uint32_t *leaf_ext = leaf_ext_all + In.L;
     uint32_t *leaf_pack = leaf_pack_all + In.P * W;
     uint64_t *split_hint = split_hint_all + In.N;
-    const int64_t S0 = (int64_t)kLeafSize << (h - jb);  // at most M
+    const int64_t S0 = 1ll << (h - jb + lsh);  // at most M
     const int64_t s0 = (int64_t)job.y * S0;
     if (s0 >= n)
         return;
@@ -753,7 +752,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
     const int w = threadIdx.x / kWave;
     const int lane = __lane_id();
     for (int l = jb; l <= h; ++l) {
-        const int S = kLeafSize << (h - l);  // node size on this level
+        const int S = 1 << (h - l + lsh);  // node size on this level
         const int nsub = (cnt0 + S - 1) / S;
         for (int u = threadIdx.x; u < nsub; u += kThreads)
 #pragma unroll
@@ -762,7 +761,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
                 s_box[u][k][1] = 0u;
             }
         __syncthreads();
-        // boxes: every 32-point group lies inside one node (S >= 32)
+        // boxes: every leaf-sized group of points lies inside one node
         for (int base = w * kWave; base < cnt0; base += kThreads) {
             const int i = base + lane;
             const bool have = i < cnt0;
@@ -770,13 +769,12 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
             for (int k = 0; k < D; ++k) {
                 uint32_t a = have ? s_x[k][i] : 0xFFFFFFFFu;
                 uint32_t b = have ? s_x[k][i] : 0u;
-#pragma unroll
-                for (int o = kLeafSize / 2; o > 0; o >>= 1) {
+                for (int o = 1 << (lsh - 1); o > 0; o >>= 1) {
                     const uint32_t ta = __shfl_xor(a, o, kWave), tb = __shfl_xor(b, o, kWave);
                     a = ta < a ? ta : a;
                     b = tb > b ? tb : b;
                 }
-                if ((i & (kLeafSize - 1)) == 0 && have) {
+                if ((i & ((1 << lsh) - 1)) == 0 && have) {
                     atomicMin(&s_box[i / S][k][0], a);
                     atomicMax(&s_box[i / S][k][1], b);
                 }
@@ -797,7 +795,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
             }
             if (l == h) {
                 // leaf record: corner (relative to the global minimum) and widest extent
-                const int64_t c = s0 / kLeafSize + u;
+                const int64_t c = (s0 >> lsh) + u;
 #pragma unroll
                 for (int k = 0; k < D; ++k)
                     leaf_org[c * D + k] = s_box[u][k][0];
@@ -1044,7 +1042,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
         sidx[s0 + i] = (int32_t)s_id[i];
         // offsets from the leaf corner, two 16-bit halves per word (read only
         // for leaves narrow enough that every offset fits)
-        const int u = i / kLeafSize;
+        const int u = i >> lsh;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             const uint32_t a = s_x[2 * w][i] - s_box[u][2 * w][0];
@@ -1095,14 +1093,14 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
             const Inst &I = ix.host[i];
             if (j >= I.jb)
                 continue;
-            const int64_t S = (int64_t)kLeafSize << (I.height - j);
+            const int64_t S = 1ll << (I.height - j + I.lsh);
             for (int64_t t = 0; t * S < I.n; ++t)
                 nodes.push_back(make_uint2((uint32_t)i, (uint32_t)t));
         }
         for (const Inst &I : ix.host) {
             if (j >= I.jb)
                 continue;
-            const int64_t node_tiles = ((int64_t)kLeafSize << (I.height - j)) / kTile;
+            const int64_t node_tiles = (1ll << (I.height - j + I.lsh)) / kTile;
             const int64_t per = node_tiles < 8 ? node_tiles : 8;
             const int64_t t_i = (I.n + kTile - 1) / kTile;
             for (int64_t q = 0; q < t_i; q += per) {
@@ -1116,7 +1114,7 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
     if (!single) {
         for (int i = 0; i < ix.count; ++i) {
             const Inst &I = ix.host[i];
-            const int64_t S0 = (int64_t)kLeafSize << (I.height - I.jb);
+            const int64_t S0 = 1ll << (I.height - I.jb + I.lsh);
             for (int64_t q = 0; q * S0 < I.n; ++q)
                 subs.push_back(make_uint2((uint32_t)i, (uint32_t)q));
         }
@@ -1174,7 +1172,7 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
             int per = 1;
             unsigned hgrid, ngrid;
             if (single) {
-                const int64_t node_tiles = ((int64_t)kLeafSize << (ix.host[0].height - j)) / kTile;
+                const int64_t node_tiles = (1ll << (ix.host[0].height - j + ix.lsh)) / kTile;
                 per = node_tiles < 8 ? (int)node_tiles : 8;
                 hgrid = (unsigned)((tiles + per - 1) / per);
                 ngrid = 1u << j;
@@ -1218,8 +1216,14 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
         }
     }
     const unsigned bgrid = single ? (unsigned)(1ll << ix.host[0].jb) : (unsigned)subs.size();
-    hipLaunchKernelGGL((k_bottom<C, D>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst, single ? nullptr : d_subs, XA, XB,
-                       IA, IB, np, box, ix.rbox, coords, ix.sidx, ix.leaf_org, ix.leaf_ext, ix.leaf_pack, ix.split);
+    if (ix.lsh == kMinLeafLog2)
+        hipLaunchKernelGGL((k_bottom<C, D, kMinLeafLog2>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst,
+                           single ? nullptr : d_subs, XA, XB, IA, IB, np, box, ix.rbox, coords, ix.sidx, ix.leaf_org,
+                           ix.leaf_ext, ix.leaf_pack, ix.split);
+    else
+        hipLaunchKernelGGL((k_bottom<C, D, kMaxLeafLog2>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst,
+                           single ? nullptr : d_subs, XA, XB, IA, IB, np, box, ix.rbox, coords, ix.sidx, ix.leaf_org,
+                           ix.leaf_ext, ix.leaf_pack, ix.split);
     DPC_HIP(hipGetLastError());
     return DPC_OK;
 }

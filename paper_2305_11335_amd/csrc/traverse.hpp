@@ -76,14 +76,16 @@ __device__ inline int64_t wave_base(int block_threads) {
     return (int64_t)blockIdx.x * block_threads + (int64_t)w * kWave;
 }
 
-// First sorted position and number of points below node v at `depth`.
-// Computed in 32 bits (scalar instructions; there is no 64-bit scalar
-// compare): n < 2^31 and a tree has at most 2^26 leaves of 32 points, so
-// every position and node capacity fits.
-__device__ inline void node_range(uint32_t v, int depth, int height, int64_t n, int64_t &start, int64_t &count) {
-    const int sh = height - depth;
-    const uint32_t st = ((v - (1u << depth)) << sh) * (uint32_t)kLeafSize;
-    const uint32_t cap = (uint32_t)kLeafSize << sh;
+// First sorted position and number of points below node v at `depth` of a
+// tree with 2^height leaves of 2^lsh points.  Computed in 32 bits (scalar
+// instructions; there is no 64-bit scalar compare): n < 2^31 and a tree's
+// leaves hold fewer than 2^32 positions, so every position and node capacity
+// fits.
+__device__ inline void node_range(uint32_t v, int depth, int height, int lsh, int64_t n, int64_t &start,
+                                  int64_t &count) {
+    const int sh = height - depth + lsh;
+    const uint32_t st = (v - (1u << depth)) << sh;
+    const uint32_t cap = 1u << sh;
     const uint32_t nn = (uint32_t)n;
     const uint32_t left = st < nn ? nn - st : 0u;
     start = st;

@@ -30,7 +30,8 @@ def _declared():
 def test_header_declares_the_interface():
     assert _declared() == sorted(["dpc_batch_run", "dpc_cluster", "dpc_density", "dpc_dependent", "dpc_last_stats",
                                   "dpc_run", "dpc_square_threshold", "dpc_status_str", "dpc_workspace_bytes",
-                                  "dpc_density_sweep", "dpc_cluster_sweep",
+                                  "dpc_density_sweep", "dpc_cluster_sweep", "dpc_set_leaf_size", "dpc_leaf_size",
+                                  "dpc_autotune",
                                   "dpc_server_create", "dpc_server_submit", "dpc_server_poll", "dpc_server_wait",
                                   "dpc_server_get_stats", "dpc_server_destroy"])
 
@@ -213,3 +214,20 @@ def test_sweep_argument_errors():
     assert lib.dpc_cluster_sweep(10, None, None, None, rm, dm, 1, None, None) == E  # null arrays
     assert lib.dpc_cluster_sweep(10, None, None, None, rm, dm, 65536, None, None) == E
     assert lib.dpc_cluster_sweep(0, None, None, None, rm, dm, 1, None, None) == 0
+
+
+def test_leaf_size_setting_is_host_only():
+    for d in range(1, 9):
+        assert dpc.leaf_size(d) in (16, 32)
+    assert dpc.load().dpc_leaf_size(0) == 0 and dpc.load().dpc_leaf_size(9) == 0
+    before = dpc.leaf_size(5)
+    for size in (16, 32):
+        dpc.set_leaf_size(5, size)
+        assert dpc.leaf_size(5) == size
+    dpc.set_leaf_size(5, before)
+    for d, size in ((0, 16), (9, 32), (3, 8), (3, 64), (2, 31)):
+        with pytest.raises(dpc.DPCError):
+            dpc.set_leaf_size(d, size)
+    lib = dpc.load()
+    assert lib.dpc_autotune(None, 10, 2, 1.0, 0, 1.0, None, None, None) == dpc._binding.ERR_INVALID_ARG
+    assert lib.dpc_autotune(None, 0, 2, 1.0, 0, 1.0, None, None, None) == dpc._binding.ERR_INVALID_ARG

@@ -29,19 +29,36 @@ struct Lo {
 
 // One candidate: keep the lexicographic minimum of (D^2, index) over points
 // of higher priority; a larger low key word means a smaller index.
-// Branch-free: the distance is formed for every candidate and the better
-// pair selected, which is cheaper than diverging per candidate.
-template <typename C, int D, bool STATS>
-__device__ inline void consider(const C (&x)[D], const C (&q)[D], uint64_t kj, uint64_t kq, C &best,
-                                uint32_t &best_low, uint64_t &n_pairs) {
-    const bool higher = kj > kq;
-    if (STATS)
-        n_pairs += higher ? 1u : 0u;
-    const C s = dist2<C, D>(x, q);
+template <typename C>
+__device__ inline void update_best(C s, uint64_t kj, uint64_t kq, C &best, uint32_t &best_low) {
     const uint32_t low = (uint32_t)kj;
-    const bool better = higher & ((s < best) | ((s == best) & (low > best_low)));
+    const bool better = (kj > kq) & ((s < best) | ((s == best) & (low > best_low)));
     best = better ? s : best;
     best_low = better ? low : best_low;
+}
+
+// kB candidates q[0..kB): most are no nearer than the best so far, so the
+// distances and that test come first for the whole batch, and the wave takes
+// the lexicographic update only when some lane has a candidate at most as
+// near (the best only shrinks, so testing against the best from before the
+// batch misses nothing).
+template <typename C, int D, bool STATS, int kB>
+__device__ inline void consider_batch(const C (&x)[D], const C (&q)[kB][D], const uint64_t (&kj)[kB], uint64_t kq,
+                                      C &best, uint32_t &best_low, uint64_t &n_pairs) {
+    C s[kB];
+    uint64_t any = 0;  // lanes with a candidate (wave masks, combined in scalar registers)
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+        if (STATS)
+            n_pairs += kj[b] > kq ? 1u : 0u;
+        s[b] = dist2<C, D>(x, q[b]);
+        any |= __builtin_amdgcn_ballot_w64(kj[b] > kq) & __builtin_amdgcn_ballot_w64(s[b] <= best);
+    }
+    if (__builtin_expect(any != 0, 0)) {
+#pragma unroll
+        for (int b = 0; b < kB; ++b)
+            update_best<C>(s[b], kj[b], kq, best, best_low);
+    }
 }
 
 // GROUP = false: one instance, whose arrays and parameters are the kernel's
@@ -143,12 +160,27 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                     }
                     wave_lds_sync();
                     if (want) {
-                        for (int t = 0; t < (int)count; ++t) {
-                            C qv[D];
+                        constexpr int kB = D <= 2 ? 4 : (D <= 4 ? 2 : 1);
+                        int t = 0;
+                        for (; t + kB <= (int)count; t += kB) {
+                            C qv[kB][D];
+                            uint64_t kv[kB];
+#pragma unroll
+                            for (int b = 0; b < kB; ++b) {
+                                kv[b] = sk[t + b];
+#pragma unroll
+                                for (int k = 0; k < D; ++k)
+                                    qv[b][k] = sp[(t + b) * D + k];
+                            }
+                            consider_batch<C, D, STATS, kB>(x, qv, kv, kq, best, best_low, n_pairs);
+                        }
+                        for (; t < (int)count; ++t) {
+                            C qv[1][D];
+                            const uint64_t kv[1] = {sk[t]};
 #pragma unroll
                             for (int k = 0; k < D; ++k)
-                                qv[k] = sp[t * D + k];
-                            consider<C, D, STATS>(x, qv, sk[t], kq, best, best_low, n_pairs);
+                                qv[0][k] = sp[t * D + k];
+                            consider_batch<C, D, STATS, 1>(x, qv, kv, kq, best, best_low, n_pairs);
                         }
                     }
                     wave_lds_sync();

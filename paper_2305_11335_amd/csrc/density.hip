@@ -344,31 +344,22 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
     };
 
     if constexpr (INTBOX) {
-        // Integer boxes, with the next boxes loaded ahead: while node v is
-        // tested, both its children's boxes (adjacent in memory) are already
-        // on their way, and a left child keeps its sibling's box for the
-        // step after it.
+        // Integer boxes (relative to the instance's minimum corner), read
+        // with scalar loads at each node: a node's box shares a cache line
+        // with its sibling's.
         constexpr int B = 2 * D;
-        uint32_t cur[B], sib[B];
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            cur[i] = rbox[(size_t)v * B + i];
-            sib[i] = 0u;
-        }
         for (;;) {
             int64_t start, count;
             node_range(v, depth, height, lsh, n, start, count);
             const bool internal = v < first_leaf;
-            uint32_t kids[2 * B];
-            if (internal) {
-#pragma unroll
-                for (int i = 0; i < 2 * B; ++i)
-                    kids[i] = rbox[(size_t)(2 * v) * B + i];
-            }
             bool descend = false;
             if (count > 0) {
                 if (STATS)
                     ++w_nodes;
+                uint32_t cur[B];
+#pragma unroll
+                for (int i = 0; i < B; ++i)
+                    cur[i] = rbox[(size_t)v * B + i];
                 bool partial = false;
                 if (settled >= depth) {
                     settled = INT_MAX;
@@ -386,19 +377,6 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
             if (descend) {
                 v <<= 1;
                 ++depth;
-#pragma unroll
-                for (int i = 0; i < B; ++i) {
-                    cur[i] = kids[i];
-                    sib[i] = kids[B + i];
-                }
-                continue;
-            }
-            if (depth > sd && (v & 1u) == 0) {
-                // a left child: its sibling's box came with it
-                v += 1;
-#pragma unroll
-                for (int i = 0; i < B; ++i)
-                    cur[i] = sib[i];
                 continue;
             }
             while (depth > sd && (v & 1u)) {
@@ -408,9 +386,6 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
             if (depth == sd)
                 break;
             v += 1;
-#pragma unroll
-            for (int i = 0; i < B; ++i)
-                cur[i] = rbox[(size_t)v * B + i];
         }
     } else {
         for (;;) {

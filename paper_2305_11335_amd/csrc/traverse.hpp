@@ -11,10 +11,21 @@
 
 #include "dpc_internal.hpp"
 
+#include <type_traits>
+
 namespace dpc {
 
 // Squared distance from a point to a box (0 inside) and to the box's
 // farthest corner.  Exact for both coordinate types on the chosen path.
+// max of two values; on the double path (never NaN here) one v_max_f64
+template <typename C>
+__device__ inline C max2(C a, C b) {
+    if constexpr (std::is_same<C, double>::value)
+        return __builtin_fmax(a, b);
+    else
+        return a > b ? a : b;
+}
+
 template <typename C, int D>
 __device__ inline void box_dist2(const C (&x)[D], const C *__restrict__ b, C &dmin2, C &dmax2) {
     C mn = 0, mx = 0;
@@ -23,9 +34,8 @@ __device__ inline void box_dist2(const C (&x)[D], const C *__restrict__ b, C &dm
         const C lo = b[2 * k], hi = b[2 * k + 1];
         const C a = lo - x[k];
         const C c = x[k] - hi;
-        C near = a > c ? a : c;
-        near = near > C(0) ? near : C(0);
-        const C far = -a > -c ? -a : -c;
+        const C near = max2<C>(max2<C>(a, c), C(0));
+        const C far = max2<C>(-a, -c);
         mn += near * near;
         mx += far * far;
     }
@@ -40,8 +50,7 @@ __device__ inline C box_min_dist2(const C (&x)[D], const C *__restrict__ b) {
     for (int k = 0; k < D; ++k) {
         const C a = b[2 * k] - x[k];
         const C c = x[k] - b[2 * k + 1];
-        C near = a > c ? a : c;
-        near = near > C(0) ? near : C(0);
+        const C near = max2<C>(max2<C>(a, c), C(0));
         mn += near * near;
     }
     return mn;

@@ -64,15 +64,15 @@ __global__ __launch_bounds__(kThreads) void k_roots(int64_t n, const int32_t *__
             __hip_atomic_store(flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }
-        const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (p == x)
             break;
-        const int32_t g = __hip_atomic_load(&par[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t g = __hip_atomic_load(&par[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (g == p) {
             x = p;
             break;
         }
-        __hip_atomic_store(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         x = g;
     }
     label[i] = x;
@@ -91,8 +91,8 @@ __global__ __launch_bounds__(kThreads) void k_parent_group(const Inst *__restric
     if (i >= I.n)
         return;
     int32_t p = (int32_t)i;
-    if (I.rho[i] >= I.rho_min && I.delta2[i] < I.Td)
-        p = I.dep[i];
+    if (global_ptr(I.rho)[i] >= I.rho_min && global_ptr(I.delta2)[i] < I.Td)
+        p = global_ptr(I.dep)[i];
     par[pos] = p;
 }
 
@@ -103,26 +103,27 @@ __global__ __launch_bounds__(kThreads) void k_roots_group(const Inst *__restrict
     const int64_t i = pos - I.P;
     if (i >= I.n)
         return;
-    if (I.rho[i] < I.rho_min) {
-        I.label[i] = -1;
+    __attribute__((address_space(1))) int32_t *label = global_ptr(I.label);
+    if (global_ptr(I.rho)[i] < I.rho_min) {
+        label[i] = -1;
         return;
     }
     int32_t *par = par_all + I.P;
     int32_t x = (int32_t)i;
     // a chain of strictly rising priorities has fewer than n edges
     for (int64_t steps = 0; steps <= I.n; ++steps) {
-        const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (p == x)
             break;
-        const int32_t g = __hip_atomic_load(&par[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t g = __hip_atomic_load(&par[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (g == p) {
             x = p;
             break;
         }
-        __hip_atomic_store(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         x = g;
     }
-    I.label[i] = x;
+    label[i] = x;
 }
 
 // One parent array per parameter pair (blockIdx.y), with the checks of
@@ -170,15 +171,15 @@ __global__ __launch_bounds__(kThreads) void k_roots_sweep(int64_t n, const int32
     int32_t x = (int32_t)i;
     // every followed edge rises (checked), so a chain has fewer than n edges
     for (int64_t steps = 0; steps <= n; ++steps) {
-        const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (p == x)
             break;
-        const int32_t g = __hip_atomic_load(&par[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t g = __hip_atomic_load(&par[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (g == p) {
             x = p;
             break;
         }
-        __hip_atomic_store(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         x = g;
     }
     label[i] = x;

@@ -225,6 +225,7 @@ struct TopArrays {
 struct NodeSelect {
     int axis;
     uint32_t base;  // the box minimum along the axis; select works on x - base
+    int bits;       // bits of the axis extent
     int passes;     // digits of the axis extent
 };
 
@@ -233,8 +234,19 @@ __device__ inline NodeSelect node_select(const uint32_t *__restrict__ nbox) {
     NodeSelect s;
     s.axis = longest_axis<D>(nbox);
     s.base = nbox[2 * s.axis];
-    s.passes = (int)((bit_length(nbox[2 * s.axis + 1] - s.base) + BITS - 1) / BITS);
+    s.bits = (int)bit_length(nbox[2 * s.axis + 1] - s.base);
+    s.passes = (s.bits + BITS - 1) / BITS;
     return s;
+}
+
+// Bits [lo, hi) of x - base form the digit of a select pass: the passes take
+// BITS bits each from the top, and the last one the few that remain.  (The
+// first passes, which see every point, thus spread them over all bins; a
+// short digit, whose few bins would collect every point, is left for the
+// last pass, which only sees the points that matched the prefix.)
+__host__ __device__ inline void digit_bits(int bits, int pass, int width, int &lo, int &hi) {
+    hi = bits - pass * width;
+    lo = hi > width ? hi - width : 0;
 }
 
 // State of a node's radix select after some passes: the digits of the
@@ -248,7 +260,7 @@ struct SelectState {
 // Chooses the digit of one pass from the node's histogram of that pass (all
 // threads of the block take part).
 template <int BITS>
-__device__ inline void pick_digit(const uint32_t *__restrict__ hp, SelectState &st, uint32_t *s_w,
+__device__ inline void pick_digit(const uint32_t *__restrict__ hp, int width, SelectState &st, uint32_t *s_w,
                                   uint32_t *s_pick) {
     using Dg = Digit<BITS>;
     uint32_t c[Dg::kPerThread];
@@ -270,7 +282,7 @@ __device__ inline void pick_digit(const uint32_t *__restrict__ hp, SelectState &
     __syncthreads();
     const uint32_t dg = s_pick[0], below = s_pick[1];
     __syncthreads();
-    st.prefix = (st.prefix << BITS) | dg;
+    st.prefix = (st.prefix << width) | dg;
     st.less += below;
     st.rank -= below;
 }
@@ -309,7 +321,9 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const Inst *__restrict__ 
         return;  // this node's median is already known (or it has no right half)
     const SelectState *state = static_cast<const SelectState *>(A.state) + I.S;
     const SelectState st = pass == 0 ? SelectState{0u, 0u, (uint32_t)tt.g.half} : state[tt.t];
-    const int shift = (ns.passes - 1 - pass) * BITS;
+    int lo, hi;
+    digit_bits(ns.bits, pass, BITS, lo, hi);
+    const uint32_t dmask = (1u << (hi - lo)) - 1u;
     for (int b = threadIdx.x; b < Dg::kBins; b += kThreads)
         s_h[b] = 0;
     __syncthreads();
@@ -325,8 +339,8 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const Inst *__restrict__ 
         for (int r = 0; r < kItems; ++r) {
             const int64_t e = e0 + (int64_t)w * kWaveItems + (int64_t)r * kWave + __lane_id();
             const uint64_t v = (uint64_t)(xv[r] - ns.base);
-            const bool match = e < n && (v >> (shift + BITS)) == (uint64_t)st.prefix;
-            const uint32_t dg = (uint32_t)(v >> shift) & (Dg::kBins - 1);
+            const bool match = e < n && (v >> hi) == (uint64_t)st.prefix;
+            const uint32_t dg = (uint32_t)(v >> lo) & dmask;
             // clustered points often share one digit across the wave: one
             // addition then serves them all
             const uint64_t mm = __ballot(match);
@@ -367,9 +381,11 @@ __global__ __launch_bounds__(kThreads) void k_sel_pick(const Inst *__restrict__ 
         return;
     SelectState *state = static_cast<SelectState *>(A.state) + I.S;
     SelectState st = pass == 0 ? SelectState{0u, 0u, (uint32_t)tt.g.half} : state[tt.t];
+    int lo, hi;
+    digit_bits(ns.bits, pass, BITS, lo, hi);
     pick_digit<BITS>(A.hist + I.H + hist_words_below(j, I.wbits) + (int64_t)pass * (1ll << j) * Dg::kBins +
                          tt.t * Dg::kBins,
-                     st, s_w, s_pick);
+                     hi - lo, st, s_w, s_pick);
     if (threadIdx.x == 0)
         state[tt.t] = st;
 }
@@ -815,6 +831,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
             const int half = cnt < S / 2 ? cnt : S / 2;
             const int a = longest_axis<D>(&s_box[u][0][0]);
             const uint32_t lo = s_box[u][a][0];
+            const int bits = (int)bit_length(s_box[u][a][1] - lo);
             int passes_max = 0, passes = 0;
             for (int uu = 0; uu < nsub; ++uu) {
                 const int b_u = uu * S;
@@ -834,15 +851,17 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
             uint32_t prefix = 0, rank = (uint32_t)half;
             for (int p = 0; p < passes_max; ++p) {
                 const bool act = p < passes;
-                const int shift = (passes - 1 - p) * kB;
+                int dlo, dhi;
+                digit_bits(bits, p, kB, dlo, dhi);
+                const uint32_t dmask = (1u << (dhi - dlo)) - 1u;
                 for (int b = sw * kWave + lane; b < kNB; b += G * kWave)
                     s_hist[u][b] = 0u;
                 __syncthreads();
                 if (act) {
                     for (int i = c_begin + lane; i < c_end; i += kWave) {
                         const uint64_t v = (uint64_t)(s_x[a][base + i] - lo);
-                        if ((v >> (shift + kB)) == (uint64_t)prefix)
-                            atomicAdd(&s_hist[u][(uint32_t)(v >> shift) & (kNB - 1)], 1u);
+                        if ((v >> dhi) == (uint64_t)prefix)
+                            atomicAdd(&s_hist[u][(uint32_t)(v >> dlo) & dmask], 1u);
                     }
                 }
                 __syncthreads();
@@ -866,7 +885,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
                 }
                 __syncthreads();
                 if (act) {
-                    prefix = (prefix << kB) | s_pick[u][0];
+                    prefix = (prefix << (dhi - dlo)) | s_pick[u][0];
                     rank -= s_pick[u][1];
                 }
             }
@@ -931,10 +950,13 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
             }
             const int a = longest_axis<D>(&s_box[u][0][0]);
             const uint32_t lo = s_box[u][a][0];
-            const int passes = (int)((bit_length(s_box[u][a][1] - lo) + kB - 1) / kB);
+            const int bits = (int)bit_length(s_box[u][a][1] - lo);
+            const int passes = (bits + kB - 1) / kB;
             uint32_t prefix = 0, rank = (uint32_t)half;
             for (int p = 0; p < passes; ++p) {
-                const int shift = (passes - 1 - p) * kB;
+                int dlo, dhi;
+                digit_bits(bits, p, kB, dlo, dhi);
+                const uint32_t dmask = (1u << (dhi - dlo)) - 1u;
                 // The histogram is shared by the lanes of this wave: every
                 // access is atomic and the phases are fenced at wavefront
                 // scope, so no lane's own store can stand in for what the
@@ -946,8 +968,8 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
                 wave_sync();
                 for (int i = lane; i < cnt; i += kWave) {
                     const uint64_t v = (uint64_t)(s_x[a][base + i] - lo);
-                    if ((v >> (shift + kB)) == (uint64_t)prefix)
-                        __hip_atomic_fetch_add(&s_hist[w][(uint32_t)(v >> shift) & (kNB - 1)], 1u, __ATOMIC_RELAXED,
+                    if ((v >> dhi) == (uint64_t)prefix)
+                        __hip_atomic_fetch_add(&s_hist[w][(uint32_t)(v >> dlo) & dmask], 1u, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WAVEFRONT);
                 }
                 wave_sync();
@@ -977,7 +999,7 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
                 const int src = __ffsll((unsigned long long)fm) - 1;
                 pick = (uint32_t)__builtin_amdgcn_readlane((int)pick, src);
                 below = (uint32_t)__builtin_amdgcn_readlane((int)below, src);
-                prefix = (prefix << kB) | pick;
+                prefix = (prefix << (dhi - dlo)) | pick;
                 rank -= below;
             }
             const uint32_t median = prefix, need_eq = rank;

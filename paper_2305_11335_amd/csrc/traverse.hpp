@@ -95,10 +95,12 @@ __device__ inline void node_range(uint32_t v, int depth, int height, int lsh, in
     const int sh = height - depth + lsh;
     const uint32_t st = (v - (1u << depth)) << sh;
     const uint32_t cap = 1u << sh;
-    const uint32_t nn = (uint32_t)n;
-    const uint32_t left = st < nn ? nn - st : 0u;
+    // (signed: st and n are below 2^31, and a signed max stays on the scalar
+    // unit where an unsigned saturating subtraction would not)
+    int32_t left = (int32_t)n - (int32_t)st;
+    left = left > 0 ? left : 0;
     start = st;
-    count = left < cap ? left : cap;
+    count = (uint32_t)left < cap ? (uint32_t)left : cap;
 }
 
 // Orders a wavefront's LDS writes before its later LDS reads (and the reads

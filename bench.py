@@ -280,6 +280,41 @@ def served(torch, dpc, pool, pts, seconds: float, warm: float, rate: float = 200
     return rec
 
 
+def planned(torch, dpc, pool, pts, calls: int = 200) -> dict:
+    """Per-call latency of one served-size instance: dpc_run against a plan
+    replayed eagerly and as a HIP graph (each call waited for)."""
+    import numpy as np
+
+    x, P = pool[0], pts[0]
+    s = torch.cuda.Stream()
+    res = {"workload": "served_3d_instance", "n": int(x.points.shape[0]), "d": int(x.points.shape[1]),
+           "calls": calls}
+    with torch.cuda.stream(s):
+        ref = [t.cpu() for t in dpc.run(P, x.d_cut, x.rho_min, x.delta_min, stream=s)]
+
+    def timed(call):
+        lat = []
+        for _ in range(10):
+            call()
+        s.synchronize()
+        for _ in range(calls):
+            t0 = time.perf_counter()
+            call()
+            s.synchronize()
+            lat.append((time.perf_counter() - t0) * 1000.0)
+        return {"p50_ms": float(np.percentile(lat, 50)), "mean_ms": float(np.mean(lat))}
+
+    res["run"] = timed(lambda: dpc.run(P, x.d_cut, x.rho_min, x.delta_min, stream=s))
+    with dpc.Plan(P, x.d_cut, x.rho_min, x.delta_min, stream=s) as plan:
+        res["plan_replay"] = timed(lambda: plan.launch(s))
+        same = all(torch.equal(a.cpu(), b) for a, b in zip(plan.out, ref))
+        plan.capture(s)
+        res["plan_graph"] = timed(lambda: plan.launch(s))
+        same = same and all(torch.equal(a.cpu(), b) for a, b in zip(plan.out, ref)) and plan.status(s) == 0
+    res["outputs_identical"] = bool(same)
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -384,6 +419,8 @@ def main() -> int:
         print("bench: served workload under overload (1500 requests/s, 7 s, twice)", file=sys.stderr, flush=True)
         rec["served_overload"] = served(torch, dpc, pool, pts, 6.0, 1.0, rate=1500.0, seed=56)
         rec["served_overload"]["workload"] = "served_poisson1500_3d"
+        print("bench: per-call latency, dpc_run against plans", file=sys.stderr, flush=True)
+        rec["planned"] = planned(torch, dpc, pool, pts)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(inst)

@@ -240,6 +240,49 @@ DPC_API int dpc_batch_run(dpc_instance *instances, int32_t count, uint32_t flags
 DPC_API uint64_t dpc_workspace_bytes(int64_t n, int32_t d);
 
 /*
+ * Plans: a dpc_run recorded once and replayed.  dpc_plan_create runs dpc_run
+ * on the given arguments (same outputs, same errors) and keeps its workspace
+ * and its sequence of kernel launches, arguments included.  A replay
+ * (dpc_plan_launch) enqueues that sequence again on any stream with no host
+ * work, no allocation and no synchronisation: it reads the CURRENT contents
+ * of `points` and overwrites rho, dep, delta2 and label, exactly as dpc_run
+ * would for those contents, provided every coordinate still lies inside the
+ * per-axis bounds measured when the plan was made.  Each replay checks this
+ * on the device and records DPC_OK or DPC_ERR_RANGE in the plan's status
+ * word (dpc_plan_status); after DPC_ERR_RANGE that replay's outputs are
+ * unspecified (coordinates are clamped into the planned bounds, so the
+ * replay stays within its buffers).  n, d, d_cut, rho_min, delta_min,
+ * flags, the pointers and the leaf size are fixed at creation.
+ *
+ * dpc_plan_capture turns the sequence into a HIP graph (captured on the
+ * given non-null stream, which must not be capturing already); later
+ * dpc_plan_launch calls launch the graph.  The graph holds no memset or copy
+ * nodes.  Replays of one plan that overlap in time race on its workspace and
+ * outputs: order them on one stream or with events.  The caller keeps the
+ * input and output buffers alive while the plan is used.
+ *
+ * dpc_plan_create: arguments as for dpc_run (flags: 0 or
+ *   DPC_SKIP_NOISE_DEPENDENTS); *out receives the plan (NULL on error).
+ *   Synchronises the stream.  The plan holds dpc_workspace_bytes(n, d) at
+ *   most, until destroyed.
+ * dpc_plan_launch: enqueues one replay on `stream`.
+ * dpc_plan_capture: DPC_ERR_INVALID_ARG for a NULL stream or a plan already
+ *   captured; DPC_ERR_HIP if capture fails (the plan stays usable uncaptured).
+ * dpc_plan_status: copies the status word of the last replay (DPC_OK before
+ *   any) to *status after the work on `stream` completes.
+ * dpc_plan_destroy: waits for the device to go idle, then frees the plan.
+ */
+typedef struct dpc_plan dpc_plan; /* opaque */
+
+DPC_API int dpc_plan_create(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,
+                            double delta_min, uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2,
+                            int32_t *label, hipStream_t stream, dpc_plan **out);
+DPC_API int dpc_plan_launch(dpc_plan *plan, hipStream_t stream);
+DPC_API int dpc_plan_capture(dpc_plan *plan, hipStream_t stream);
+DPC_API int dpc_plan_status(dpc_plan *plan, hipStream_t stream, int32_t *status);
+DPC_API int dpc_plan_destroy(dpc_plan *plan);
+
+/*
  * Served clustering (the batching of dpc_batch_run applied to a stream of
  * requests).  A server owns `slots` host threads, each with a HIP stream of
  * its own on the device current at creation.  Requests wait in one queue in

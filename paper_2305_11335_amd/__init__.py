@@ -12,6 +12,7 @@ from ._binding import (  # noqa: F401
     EXPORTED,
     INF,
     LIB_PATH,
+    Plan,
     SKIP_NOISE_DEPENDENTS,
     STAGES,
     Server,

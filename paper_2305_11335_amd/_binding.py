@@ -24,7 +24,8 @@ EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_batch
             "dpc_status_str", "dpc_square_threshold", "dpc_workspace_bytes", "dpc_density_sweep",
             "dpc_cluster_sweep", "dpc_server_create",
             "dpc_server_submit", "dpc_server_poll", "dpc_server_wait", "dpc_server_get_stats",
-            "dpc_server_destroy", "dpc_set_leaf_size", "dpc_leaf_size", "dpc_autotune")
+            "dpc_server_destroy", "dpc_set_leaf_size", "dpc_leaf_size", "dpc_autotune", "dpc_plan_create",
+            "dpc_plan_launch", "dpc_plan_capture", "dpc_plan_status", "dpc_plan_destroy")
 
 
 class Stats(ctypes.Structure):
@@ -122,6 +123,16 @@ def load():
     lib.dpc_server_get_stats.restype = ctypes.c_int
     lib.dpc_server_destroy.argtypes = [P]
     lib.dpc_server_destroy.restype = ctypes.c_int
+    lib.dpc_plan_create.argtypes = [P, i64, i32, dbl, i32, dbl, u32, P, P, P, P, P, ctypes.POINTER(P)]
+    lib.dpc_plan_create.restype = ctypes.c_int
+    lib.dpc_plan_launch.argtypes = [P, P]
+    lib.dpc_plan_launch.restype = ctypes.c_int
+    lib.dpc_plan_capture.argtypes = [P, P]
+    lib.dpc_plan_capture.restype = ctypes.c_int
+    lib.dpc_plan_status.argtypes = [P, P, ctypes.POINTER(i32)]
+    lib.dpc_plan_status.restype = ctypes.c_int
+    lib.dpc_plan_destroy.argtypes = [P]
+    lib.dpc_plan_destroy.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -420,6 +431,67 @@ class Server:
             self._keep.clear()
             if st != OK:
                 raise DPCError(st, "dpc_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Plan:
+    """A dpc_plan: run() recorded once on `points` and the output tensors,
+    then replayed with launch() (optionally as a HIP graph after capture())
+    on the current contents of `points` (see include/libdpc.h)."""
+
+    def __init__(self, points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool = False, out=None,
+                 stream=None):
+        torch = _torch()
+        n, d = _check_points(points)
+        dev = points.device
+        o = out if out is not None else (None, None, None, None)
+        self.out = (_out(o[0], n, torch.int32, dev), _out(o[1], n, torch.int32, dev),
+                    _out(o[2], n, torch.int64, dev), _out(o[3], n, torch.int32, dev))
+        self.points = points
+        self._h = ctypes.c_void_p()
+        st = load().dpc_plan_create(_ptr(points), n, d, float(d_cut), int(rho_min), float(delta_min),
+                                    SKIP_NOISE_DEPENDENTS if skip_noise else 0, _ptr(self.out[0]),
+                                    _ptr(self.out[1]), _ptr(self.out[2]), _ptr(self.out[3]), _stream(stream),
+                                    ctypes.byref(self._h))
+        if st != OK:
+            raise DPCError(st, "dpc_plan_create")
+
+    def launch(self, stream=None):
+        """Enqueues one replay; returns the output tensors."""
+        st = load().dpc_plan_launch(self._h, _stream(stream))
+        if st != OK:
+            raise DPCError(st, "dpc_plan_launch")
+        return self.out
+
+    def capture(self, stream=None):
+        """Captures the replay into a HIP graph on a non-default stream."""
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.Stream()
+        st = load().dpc_plan_capture(self._h, _stream(stream))
+        if st != OK:
+            raise DPCError(st, "dpc_plan_capture")
+
+    def status(self, stream=None) -> int:
+        """The last replay's status (OK, or ERR_RANGE if the points left the
+        planned bounds); waits for `stream`."""
+        v = ctypes.c_int32()
+        st = load().dpc_plan_status(self._h, _stream(stream), ctypes.byref(v))
+        if st != OK:
+            raise DPCError(st, "dpc_plan_status")
+        return v.value
+
+    def close(self):
+        if self._h:
+            st = load().dpc_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            if st != OK:
+                raise DPCError(st, "dpc_plan_destroy")
 
     def __enter__(self):
         return self

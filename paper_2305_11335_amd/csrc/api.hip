@@ -59,6 +59,9 @@ dpc_status square_threshold(double r, bool round_up, int64_t *out) {
     return DPC_OK;
 }
 
+thread_local LaunchRecord *t_record = nullptr;
+thread_local int32_t *t_plan_status = nullptr;
+
 hipMemPool_t workspace_pool() {
     static std::mutex mu;
     static hipMemPool_t pools[64] = {};
@@ -318,6 +321,16 @@ dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int cou
 
 }  // namespace dpc
 
+// A recorded dpc_run: its workspace stays allocated and its kernel launches
+// (with their argument values) are kept for replay.
+struct dpc_plan {
+    dpc::Workspace *ws = nullptr;
+    dpc::LaunchRecord ops;
+    int32_t *status = nullptr;  // device word set by every replay's bounds check
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 using namespace dpc;
 
 extern "C" {
@@ -478,7 +491,7 @@ int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t r
     int64_t *counters = nullptr;
     if (flags & DPC_COUNT_WORK) {
         DPC_TRY(ws.alloc(&counters, kCounters));
-        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(kWave), 0, stream, counters);
+        launch(k_zero_counters, dim3(1), dim3(kWave), 0, stream, counters);
         DPC_HIP(hipGetLastError());
     }
     std::vector<Job> jobs{J};
@@ -575,6 +588,118 @@ int dpc_autotune(const int32_t *points, int64_t n, int32_t d, double d_cut, int3
     }
     if (chosen)
         *chosen = 1 << pick;
+    return DPC_OK;
+}
+
+int dpc_plan_create(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
+                    uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2, int32_t *label, hipStream_t stream,
+                    dpc_plan **out) {
+    if (out == nullptr)
+        return DPC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (flags & ~(uint32_t)DPC_SKIP_NOISE_DEPENDENTS)
+        return DPC_ERR_INVALID_ARG;
+    Job J;
+    DPC_TRY(make_job(points, n, d, d_cut, rho_min, delta_min, flags, rho, dep, delta2, label, J));
+    dpc_plan *pl = new (std::nothrow) dpc_plan;
+    if (pl == nullptr)
+        return DPC_ERR_OOM;
+    pl->ws = new (std::nothrow) Workspace(stream);
+    if (pl->ws == nullptr) {
+        delete pl;
+        return DPC_ERR_OOM;
+    }
+    dpc_status st = DPC_OK;
+    if (n > 0) {
+        st = pl->ws->alloc(&pl->status, 1);
+        if (st == DPC_OK) {
+            t_record = &pl->ops;
+            t_plan_status = pl->status;
+            std::vector<Job> jobs{J};
+            st = job_bounds(jobs, d, *pl->ws, nullptr);
+            if (st == DPC_OK)
+                st = run_group(jobs, d, job_arith(jobs[0], d), nullptr, nullptr, *pl->ws);
+            t_record = nullptr;
+            t_plan_status = nullptr;
+        }
+        if (st == DPC_OK && hipStreamSynchronize(stream) != hipSuccess)
+            st = DPC_ERR_HIP;
+    }
+    if (st != DPC_OK) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(stream);
+        delete pl->ws;
+        delete pl;
+        return st;
+    }
+    *out = pl;
+    return DPC_OK;
+}
+
+int dpc_plan_launch(dpc_plan *plan, hipStream_t stream) {
+    if (plan == nullptr)
+        return DPC_ERR_INVALID_ARG;
+    if (plan->exec) {
+        DPC_HIP(hipGraphLaunch(plan->exec, stream));
+        return DPC_OK;
+    }
+    for (auto &op : plan->ops)
+        op(stream);
+    DPC_HIP(hipGetLastError());
+    return DPC_OK;
+}
+
+int dpc_plan_capture(dpc_plan *plan, hipStream_t stream) {
+    if (plan == nullptr || stream == nullptr || plan->exec != nullptr)
+        return DPC_ERR_INVALID_ARG;
+    DPC_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    for (auto &op : plan->ops)
+        op(stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(stream, &g);
+    if (e != hipSuccess || g == nullptr) {
+        (void)hipGetLastError();
+        return DPC_ERR_HIP;
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(g);
+        return DPC_ERR_HIP;
+    }
+    plan->graph = g;
+    plan->exec = x;
+    return DPC_OK;
+}
+
+int dpc_plan_status(dpc_plan *plan, hipStream_t stream, int32_t *status) {
+    if (plan == nullptr || status == nullptr)
+        return DPC_ERR_INVALID_ARG;
+    *status = DPC_OK;
+    if (plan->status == nullptr)
+        return DPC_OK;
+    int32_t h = 0;
+    DPC_HIP(hipMemcpyAsync(&h, plan->status, sizeof(h), hipMemcpyDeviceToHost, stream));
+    DPC_HIP(hipStreamSynchronize(stream));
+    *status = h;
+    return DPC_OK;
+}
+
+int dpc_plan_destroy(dpc_plan *plan) {
+    if (plan == nullptr)
+        return DPC_ERR_INVALID_ARG;
+    // replays may have run on any stream: let them finish before the
+    // workspace goes back to the pool
+    (void)hipDeviceSynchronize();
+    if (plan->exec)
+        (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph)
+        (void)hipGraphDestroy(plan->graph);
+    // the creating stream may be gone by now; the device is idle
+    plan->ws->stream = nullptr;
+    delete plan->ws;
+    (void)hipStreamSynchronize(nullptr);
+    delete plan;
     return DPC_OK;
 }
 

@@ -198,8 +198,8 @@ dpc_status launch_group_labels(const Index &ix, Workspace &ws) {
     int32_t *par;
     DPC_TRY(ws.alloc(&par, (size_t)ix.positions));
     const dim3 grid(blocks_for(ix.positions, kThreads)), block(kThreads);
-    hipLaunchKernelGGL(k_parent_group, grid, block, 0, s, ix.inst, ix.tile_inst, par);
-    hipLaunchKernelGGL(k_roots_group, grid, block, 0, s, ix.inst, ix.tile_inst, par);
+    launch(k_parent_group, grid, block, 0, s, ix.inst, ix.tile_inst, par);
+    launch(k_roots_group, grid, block, 0, s, ix.inst, ix.tile_inst, par);
     DPC_HIP(hipGetLastError());
     return DPC_OK;
 }
@@ -211,8 +211,8 @@ dpc_status launch_cluster(int64_t n, const int32_t *rho, const int32_t *dep, con
     DPC_TRY(ws.alloc(&par, n));
     DPC_TRY(ws.alloc(&flag, 1));
     const dim3 grid(blocks_for(n, kThreads)), block(kThreads);
-    hipLaunchKernelGGL(k_flag_init, dim3(1), dim3(kWave), 0, s, flag);
-    hipLaunchKernelGGL(k_parent, grid, block, 0, s, n, rho, dep, delta2, rho_min, Td, validate ? 1 : 0, par, flag);
+    launch(k_flag_init, dim3(1), dim3(kWave), 0, s, flag);
+    launch(k_parent, grid, block, 0, s, n, rho, dep, delta2, rho_min, Td, validate ? 1 : 0, par, flag);
     DPC_HIP(hipGetLastError());
     if (validate) {
         // an unchecked cycle would never let the walks end: check first
@@ -222,7 +222,7 @@ dpc_status launch_cluster(int64_t n, const int32_t *rho, const int32_t *dep, con
         if (h != 0)
             return DPC_ERR_NOT_FOREST;
     }
-    hipLaunchKernelGGL(k_roots, grid, block, 0, s, n, rho, rho_min, par, label, flag);
+    launch(k_roots, grid, block, 0, s, n, rho, rho_min, par, label, flag);
     DPC_HIP(hipGetLastError());
     return DPC_OK;
 }
@@ -238,9 +238,9 @@ dpc_status launch_cluster_sweep(int64_t n, const int32_t *rho, const int32_t *de
     DPC_TRY(ws.alloc(&d_Td, (size_t)count));
     DPC_HIP(hipMemcpyAsync(d_rmin, rho_mins, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
     DPC_HIP(hipMemcpyAsync(d_Td, Tds, count * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(count, kThreads)), dim3(kThreads), 0, s, flag, (int64_t)count, 0);
+    launch(k_fill_i32, dim3(blocks_for(count, kThreads)), dim3(kThreads), 0, s, flag, (int64_t)count, 0);
     const dim3 grid(blocks_for(n, kThreads), (unsigned)count), block(kThreads);
-    hipLaunchKernelGGL(k_parent_sweep, grid, block, 0, s, n, rho, dep, delta2, d_rmin, d_Td, par, flag);
+    launch(k_parent_sweep, grid, block, 0, s, n, rho, dep, delta2, d_rmin, d_Td, par, flag);
     DPC_HIP(hipGetLastError());
     // an unchecked cycle would never let the walks end: check first (this
     // also keeps the host parameter arrays alive until they are copied)
@@ -250,7 +250,7 @@ dpc_status launch_cluster_sweep(int64_t n, const int32_t *rho, const int32_t *de
     for (int32_t f : h)
         if (f != 0)
             return DPC_ERR_NOT_FOREST;
-    hipLaunchKernelGGL(k_roots_sweep, grid, block, 0, s, n, rho, d_rmin, par, label);
+    launch(k_roots_sweep, grid, block, 0, s, n, rho, d_rmin, par, label);
     DPC_HIP(hipGetLastError());
     return DPC_OK;
 }

@@ -445,7 +445,7 @@ dpc_status launch_typed(const Index &ix, int32_t *srho, int64_t *counters, hipSt
     switch (ix.d) {
 #define DPC_DENSITY_CASE(DD)                                                                                    \
     case DD:                                                                                                    \
-        hipLaunchKernelGGL((k_density<C, DD, STATS, INTBOX, LSH>), grid, block, 0, s, ix.inst, ix.tile_inst, \
+        launch((k_density<C, DD, STATS, INTBOX, LSH>), grid, block, 0, s, ix.inst, ix.tile_inst, \
                            G, counters);                                                                        \
         break;
         DPC_DENSITY_CASE(1)

@@ -261,7 +261,7 @@ dpc_status launch_typed(const Index &ix, int64_t *counters, hipStream_t s) {
     switch (ix.d) {
 #define DPC_DEP_CASE(DD)                                                                                          \
     case DD:                                                                                                      \
-        hipLaunchKernelGGL((k_dependent<C, DD, STATS, GROUP, LSH>), grid, block, 0, s, coords, box, ix.skey,     \
+        launch((k_dependent<C, DD, STATS, GROUP, LSH>), grid, block, 0, s, coords, box, ix.skey,     \
                            ix.maxkey, ix.split, lo, I.n, I.height, I.dep_rho_min, ix.sidx, I.dep, I.delta2, counters, \
                            ix.inst, ix.tile_inst);                                                                 \
         break;

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <vector>
 
 #include "../../include/libdpc.h"
@@ -278,6 +279,25 @@ dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int cou
 
 // The argument checks of dpc_run for one instance (host only).
 dpc_status check_instance(const dpc_instance &q, uint32_t flags);
+
+// Kernel launches.  Every launch of the method goes through launch(), which
+// also appends it (kernel, geometry and argument values) to the calling
+// thread's record when one is active: a plan (dpc_plan_create) records its
+// first run and later replays the same launches, with no host work, or
+// captures them into a HIP graph.
+using LaunchRecord = std::vector<std::function<void(hipStream_t)>>;
+extern thread_local LaunchRecord *t_record;
+// While a plan records: the device word its replays set to DPC_ERR_RANGE when
+// the points no longer lie inside the bounds the plan was made for (else 0).
+extern thread_local int32_t *t_plan_status;
+
+template <typename... KArgs, typename... Args>
+inline void launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t shmem, hipStream_t s, Args... args) {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+    if (t_record)
+        t_record->push_back(
+            [=](hipStream_t st) { hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...); });
+}
 
 // Kernel-launch geometry helpers.
 inline unsigned blocks_for(int64_t items, int per_block) {

@@ -58,6 +58,22 @@ __device__ inline void block_bounds(const int32_t (&lmin)[D], const int32_t (&lm
     __syncthreads();
 }
 
+// A planned replay's check: the points' bounds (mm, just computed) must lie
+// inside the bounds the plan was made for.
+struct Box {
+    int32_t lo[kMaxDim];
+    int32_t hi[kMaxDim];
+};
+
+__global__ void k_bounds_check(const int32_t *__restrict__ mm, Box planned, int d, int32_t *status) {
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        for (int k = 0; k < d; ++k)
+            ok = ok && mm[k] >= planned.lo[k] && mm[kMaxDim + k] <= planned.hi[k];
+        status[0] = ok ? 0 : (int32_t)DPC_ERR_RANGE;
+    }
+}
+
 __global__ void k_bounds_init(int32_t *mm) {
     const int t = threadIdx.x;
     if (t < kMaxDim) {
@@ -270,12 +286,12 @@ dpc_status job_bounds(std::vector<Job> &jobs, int d, Workspace &ws, std::vector<
     if (count == 1) {
         int32_t *mm;
         DPC_TRY(ws.alloc(&mm, 2 * kMaxDim));
-        hipLaunchKernelGGL(k_bounds_init, dim3(1), dim3(kWave), 0, s, mm);
+        launch(k_bounds_init, dim3(1), dim3(kWave), 0, s, mm);
         const unsigned grid = blocks_for(jobs[0].n, kThreads) < 1024u ? blocks_for(jobs[0].n, kThreads) : 1024u;
         switch (d) {
 #define DPC_BOUNDS_CASE(DD)                                                                                   \
     case DD:                                                                                                  \
-        hipLaunchKernelGGL((k_bounds<DD>), dim3(grid), dim3(kThreads), 0, s, jobs[0].points, jobs[0].n, mm); \
+        launch((k_bounds<DD>), dim3(grid), dim3(kThreads), 0, s, jobs[0].points, jobs[0].n, mm); \
         break;
             DPC_BOUNDS_CASE(1)
             DPC_BOUNDS_CASE(2)
@@ -291,6 +307,17 @@ dpc_status job_bounds(std::vector<Job> &jobs, int d, Workspace &ws, std::vector<
         }
         DPC_HIP(hipGetLastError());
         DPC_HIP(hipMemcpyAsync(host_mm.data(), mm, 2 * kMaxDim * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (t_record && t_plan_status) {
+            // a plan's replays check the points against the bounds read now
+            DPC_HIP(hipStreamSynchronize(s));
+            Box planned{};
+            for (int k = 0; k < kMaxDim; ++k) {
+                planned.lo[k] = host_mm[k];
+                planned.hi[k] = host_mm[kMaxDim + k];
+            }
+            launch(k_bounds_check, dim3(1), dim3(kWave), 0, s, (const int32_t *)mm, planned, d, t_plan_status);
+            DPC_HIP(hipGetLastError());
+        }
     } else {
         // instances laid out tile by tile, bounds per tile, then per instance
         std::vector<Inst> pre(count);
@@ -319,8 +346,8 @@ dpc_status job_bounds(std::vector<Job> &jobs, int d, Workspace &ws, std::vector<
         switch (d) {
 #define DPC_BOUNDS_CASE(DD)                                                                                     \
     case DD:                                                                                                    \
-        hipLaunchKernelGGL((k_bounds_tiles<DD>), dim3(nt), dim3(kThreads), 0, s, d_inst, d_tiles, tmm);          \
-        hipLaunchKernelGGL((k_bounds_reduce<DD>), dim3((unsigned)count), dim3(kThreads), 0, s, d_inst, tmm, mm); \
+        launch((k_bounds_tiles<DD>), dim3(nt), dim3(kThreads), 0, s, d_inst, d_tiles, tmm);          \
+        launch((k_bounds_reduce<DD>), dim3((unsigned)count), dim3(kThreads), 0, s, d_inst, tmm, mm); \
         break;
             DPC_BOUNDS_CASE(1)
             DPC_BOUNDS_CASE(2)
@@ -517,22 +544,22 @@ dpc_status build_priority(const int32_t *srho, bool rho_orig, Workspace &ws, Ind
     (void)rho_orig;  // without srho the keys read each instance's rho array
     DPC_TRY(ws.alloc(&ix.skey, (size_t)ix.positions));
     DPC_TRY(ws.alloc(&ix.maxkey, (size_t)ix.nodes));
-    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(ix.nodes, kThreads)), dim3(kThreads), 0, s, ix.maxkey, ix.nodes,
+    launch(k_fill_u64, dim3(blocks_for(ix.nodes, kThreads)), dim3(kThreads), 0, s, ix.maxkey, ix.nodes,
                        (uint64_t)0);
-    hipLaunchKernelGGL(k_keys_leaf, dim3(blocks_for(ix.positions, kThreads)), dim3(kThreads), 0, s, ix.inst,
+    launch(k_keys_leaf, dim3(blocks_for(ix.positions, kThreads)), dim3(kThreads), 0, s, ix.inst,
                        ix.tile_inst, srho, ix.sidx, ix.skey, ix.maxkey);
     if (ix.count == 1) {
         for (int depth = ix.host[0].height; depth > 0;) {
             const int lv = depth < 8 ? depth : 8;
             const int64_t nodes = 1ll << depth;
             const unsigned grid = nodes < kThreads ? 1u : (unsigned)(nodes / kThreads);
-            hipLaunchKernelGGL(k_key_up, dim3(grid), dim3(kThreads), 0, s, ix.maxkey, depth, lv);
+            launch(k_key_up, dim3(grid), dim3(kThreads), 0, s, ix.maxkey, depth, lv);
             depth -= lv;
         }
     } else {
         for (int depth = ix.max_height - 1; depth >= 0; --depth) {
             const unsigned gx = blocks_for(1ll << depth, kThreads);
-            hipLaunchKernelGGL(k_key_level, dim3(gx, (unsigned)ix.count), dim3(kThreads), 0, s, ix.inst, depth,
+            launch(k_key_level, dim3(gx, (unsigned)ix.count), dim3(kThreads), 0, s, ix.inst, depth,
                                ix.maxkey);
         }
     }

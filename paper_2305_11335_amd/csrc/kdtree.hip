@@ -690,7 +690,10 @@ __global__ void k_root_box(const Inst *__restrict__ inst, int count, uint32_t *_
 }
 
 // Coordinates relative to lo in structure-of-arrays form, and the identity
-// permutation, at every instance's positions.
+// permutation, at every instance's positions.  Each is clamped to [0, span]:
+// a no-op for bounds just measured, and on a plan's replay over points that
+// left the planned bounds (reported through the plan's status word) it keeps
+// every later extent, digit count and histogram inside what was planned.
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_soa_init(const Inst *__restrict__ inst,
                                                        const uint32_t *__restrict__ tile_inst, int64_t positions,
@@ -702,8 +705,12 @@ __global__ __launch_bounds__(kThreads) void k_soa_init(const Inst *__restrict__ 
         return;
     const int32_t *P = I.points;
 #pragma unroll
-    for (int k = 0; k < D; ++k)
-        X[(int64_t)k * positions + pos] = (uint32_t)((int64_t)P[i * D + k] - (int64_t)I.lo[k]);
+    for (int k = 0; k < D; ++k) {
+        int64_t v = (int64_t)P[i * D + k] - (int64_t)I.lo[k];
+        v = v < 0 ? 0 : v;
+        v = v > (int64_t)I.span[k] ? (int64_t)I.span[k] : v;
+        X[(int64_t)k * positions + pos] = (uint32_t)v;
+    }
     Ids[pos] = (uint32_t)i;
 }
 
@@ -1097,7 +1104,7 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
     DPC_TRY(ws.alloc(&XA, (size_t)D * np));
     DPC_TRY(ws.alloc(&IA, (size_t)np));
     DPC_TRY(upload_group(ws, ix));
-    hipLaunchKernelGGL((k_soa_init<D>), dim3(blocks_for(np, kThreads)), dim3(kThreads), 0, s, ix.inst, ix.tile_inst,
+    launch((k_soa_init<D>), dim3(blocks_for(np, kThreads)), dim3(kThreads), 0, s, ix.inst, ix.tile_inst,
                        np, XA, IA);
     DPC_HIP(hipGetLastError());
 
@@ -1177,9 +1184,9 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
         DPC_TRY(ws.alloc(&cnt_eq, (size_t)tiles));
         DPC_TRY(ws.alloc(&tile_box, (size_t)tiles * 4 * D));
         if (hist_words > 0)
-            hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(hist_words, kThreads)), dim3(kThreads), 0, s, hist,
+            launch(k_fill_u32, dim3(blocks_for(hist_words, kThreads)), dim3(kThreads), 0, s, hist,
                                hist_words, 0u);
-        hipLaunchKernelGGL((k_root_box<D>), dim3(blocks_for(ix.count, kThreads)), dim3(kThreads), 0, s, ix.inst,
+        launch((k_root_box<D>), dim3(blocks_for(ix.count, kThreads)), dim3(kThreads), 0, s, ix.inst,
                            ix.count, nboxes);
         TopArrays A{XA, np, nboxes, hist, state, splits};
         uint32_t *Iin = IA, *Xout = XB, *Iout = IB;  // level j reads buffer j mod 2
@@ -1207,27 +1214,27 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
             for (int p = 0; p < passes; ++p) {
                 if (hgrid > 0) {
                     if (bits == 11)
-                        hipLaunchKernelGGL((k_sel_hist<D, 11>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst,
+                        launch((k_sel_hist<D, 11>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst,
                                            ix.tile_inst, hb, per, A, j, p);
                     else
-                        hipLaunchKernelGGL((k_sel_hist<D, 8>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst,
+                        launch((k_sel_hist<D, 8>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst,
                                            ix.tile_inst, hb, per, A, j, p);
                 }
                 if (bits == 11)
-                    hipLaunchKernelGGL((k_sel_pick<D, 11>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, p);
+                    launch((k_sel_pick<D, 11>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, p);
                 else
-                    hipLaunchKernelGGL((k_sel_pick<D, 8>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, p);
+                    launch((k_sel_pick<D, 8>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, p);
             }
             if (bits == 11)
-                hipLaunchKernelGGL((k_part_count<C, D, 11>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst,
+                launch((k_part_count<C, D, 11>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst,
                                    A, j, cnt_less, cnt_eq, box, ix.rbox, ix.split);
             else
-                hipLaunchKernelGGL((k_part_count<C, D, 8>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst,
+                launch((k_part_count<C, D, 8>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst,
                                    A, j, cnt_less, cnt_eq, box, ix.rbox, ix.split);
-            hipLaunchKernelGGL(k_part_scan, dim3(2), dim3(kScanThreads), 0, s, cnt_less, cnt_eq, (int)tiles);
-            hipLaunchKernelGGL((k_part_scatter<D>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, A, Iin,
+            launch(k_part_scan, dim3(2), dim3(kScanThreads), 0, s, cnt_less, cnt_eq, (int)tiles);
+            launch((k_part_scatter<D>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, A, Iin,
                                Xout, Iout, j, cnt_less, cnt_eq, tile_box);
-            hipLaunchKernelGGL((k_box_reduce<D>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, tile_box);
+            launch((k_box_reduce<D>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, tile_box);
             DPC_HIP(hipGetLastError());
             uint32_t *t = A.X;
             A.X = Xout;
@@ -1239,11 +1246,11 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
     }
     const unsigned bgrid = single ? (unsigned)(1ll << ix.host[0].jb) : (unsigned)subs.size();
     if (ix.lsh == kMinLeafLog2)
-        hipLaunchKernelGGL((k_bottom<C, D, kMinLeafLog2>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst,
+        launch((k_bottom<C, D, kMinLeafLog2>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst,
                            single ? nullptr : d_subs, XA, XB, IA, IB, np, box, ix.rbox, coords, ix.sidx, ix.leaf_org,
                            ix.leaf_ext, ix.leaf_pack, ix.split);
     else
-        hipLaunchKernelGGL((k_bottom<C, D, kMaxLeafLog2>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst,
+        launch((k_bottom<C, D, kMaxLeafLog2>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst,
                            single ? nullptr : d_subs, XA, XB, IA, IB, np, box, ix.rbox, coords, ix.sidx, ix.leaf_org,
                            ix.leaf_ext, ix.leaf_pack, ix.split);
     DPC_HIP(hipGetLastError());

@@ -33,7 +33,8 @@ def test_header_declares_the_interface():
                                   "dpc_density_sweep", "dpc_cluster_sweep", "dpc_set_leaf_size", "dpc_leaf_size",
                                   "dpc_autotune",
                                   "dpc_server_create", "dpc_server_submit", "dpc_server_poll", "dpc_server_wait",
-                                  "dpc_server_get_stats", "dpc_server_destroy"])
+                                  "dpc_server_get_stats", "dpc_server_destroy", "dpc_plan_create", "dpc_plan_launch",
+                                  "dpc_plan_capture", "dpc_plan_status", "dpc_plan_destroy"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -231,3 +232,24 @@ def test_leaf_size_setting_is_host_only():
     lib = dpc.load()
     assert lib.dpc_autotune(None, 10, 2, 1.0, 0, 1.0, None, None, None) == dpc._binding.ERR_INVALID_ARG
     assert lib.dpc_autotune(None, 0, 2, 1.0, 0, 1.0, None, None, None) == dpc._binding.ERR_INVALID_ARG
+
+
+def test_plan_argument_errors():
+    lib = dpc.load()
+    E = dpc._binding.ERR_INVALID_ARG
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+    h = ctypes.c_void_p(0x1234)
+    args = (fake, 5, 2, 1.0, 0, 1.0)
+    outs = (fake, fake, fake, fake, NULL)
+    assert lib.dpc_plan_create(*args, 0, *outs, None) == E  # no place for the plan
+    assert lib.dpc_plan_create(*args, 4, *outs, ctypes.byref(h)) == E  # only the skip-noise flag
+    assert h.value is None  # cleared on error
+    assert lib.dpc_plan_create(fake, 5, 9, 1.0, 0, 1.0, 0, *outs, ctypes.byref(h)) == E
+    assert lib.dpc_plan_create(fake, 5, 2, float("nan"), 0, 1.0, 0, *outs, ctypes.byref(h)) == E
+    assert lib.dpc_plan_create(fake, 5, 2, 1.0, -1, 1.0, 0, *outs, ctypes.byref(h)) == E
+    assert lib.dpc_plan_create(*args, 0, fake, NULL, fake, fake, NULL, ctypes.byref(h)) == E
+    st = ctypes.c_int32()
+    assert lib.dpc_plan_launch(None, None) == E
+    assert lib.dpc_plan_capture(None, fake) == E
+    assert lib.dpc_plan_status(None, None, ctypes.byref(st)) == E
+    assert lib.dpc_plan_destroy(None) == E

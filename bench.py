@@ -315,6 +315,28 @@ def planned(torch, dpc, pool, pts, calls: int = 200) -> dict:
     return res
 
 
+def fenwick(torch, dpc, inst, P, want, runs: int = 3) -> dict:
+    """The whole method with the Fenwick-tree dependent backend on the
+    headline workload (per-step GPU times from HIP events), outputs compared
+    with the priority-search tree's."""
+    got = dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, fenwick=True)
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(got, want))
+    total, dep = [], []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, out=got, fenwick=True, time_stages=True)
+        st = dpc.last_stats()["stage_ms"]
+        torch.cuda.synchronize()
+        total.append((time.perf_counter() - t0) * 1000.0)
+        dep.append(st["priority"] + st["dependent"])
+    total.sort()
+    dep.sort()
+    return {"workload": inst.name, "runs": runs, "ms_per_step": total[len(total) // 2],
+            "dependent_ms": dep[len(dep) // 2], "points_per_s": inst.n / (total[len(total) // 2] / 1000.0),
+            "outputs_identical_to_priority_tree": bool(same)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -323,6 +345,7 @@ def main() -> int:
     ap.add_argument("--workload", default="varden2d_10m")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip both CPU baselines")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
+    ap.add_argument("--no-fenwick", action="store_true", help="skip the Fenwick-backend measurement")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-workload measurement")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
@@ -406,6 +429,10 @@ def main() -> int:
         "work": {k: work[k] for k in dpc.WORK_FIELDS},
         "roofline": roofline,
     }
+    if not args.no_fenwick:
+        print("bench: Fenwick-tree dependent backend", file=sys.stderr, flush=True)
+        rec["fenwick"] = fenwick(torch, dpc, inst, P, out)
+        rec["fenwick"]["priority_tree_dependent_ms"] = stage_ms["priority"] + stage_ms["dependent"]
     if not args.no_batch:
         print("bench: batched workload", file=sys.stderr, flush=True)
         rec["batched"] = batched(torch, dpc, datagen, args.batch_steps)

@@ -88,6 +88,11 @@ typedef enum {
 /* dpc_run flag: run instrumented kernels that count the work they do (slower;
  * for measurement only).  The counts are read back before the call returns. */
 #define DPC_COUNT_WORK 4u
+/* dpc_run flag: find dependent points with the Fenwick tree of k-d trees
+ * (Section 5, Algorithm 2) instead of the priority-search k-d tree
+ * (Section 4.2).  Same outputs; a different algorithm, for comparison.
+ * Work counters (DPC_COUNT_WORK) then cover the density step only. */
+#define DPC_FENWICK_DEPENDENTS 8u
 
 /* Steps of dpc_run timed by DPC_TIME_STAGES. */
 enum {
@@ -159,7 +164,8 @@ DPC_API int dpc_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const
 /*
  * The whole method: density, dependent points and labels, sharing one
  * spatial index (the three steps of Section 1).  flags: any combination of
- * DPC_SKIP_NOISE_DEPENDENTS, DPC_TIME_STAGES and DPC_COUNT_WORK.  Output
+ * DPC_SKIP_NOISE_DEPENDENTS, DPC_TIME_STAGES, DPC_COUNT_WORK and
+ * DPC_FENWICK_DEPENDENTS.  Output
  * arrays as above; all four are written.
  */
 DPC_API int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,
@@ -378,6 +384,29 @@ DPC_API int32_t dpc_leaf_size(int32_t d);
  */
 DPC_API int dpc_autotune(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,
                          double delta_min, hipStream_t stream, double *ms_out, int32_t *chosen);
+
+/*
+ * Dependent-point backend per dimension: the priority-search k-d tree
+ * (Section 4.2, the default) or the Fenwick tree of k-d trees (Section 5,
+ * Algorithm 2).  Both give the same outputs.  dpc_run uses the Fenwick tree
+ * when the setting for d says so or DPC_FENWICK_DEPENDENTS is passed; the
+ * other calls always use the priority-search tree.  The setting is
+ * process-wide.
+ * dpc_set_dependent_backend: DPC_ERR_INVALID_ARG for d outside [1, 8] or an
+ *   unknown backend.
+ * dpc_dependent_backend: the current backend for d (-1 for an invalid d).
+ * dpc_autotune_dependent: runs the whole method on the given instance with
+ *   each backend (one warm-up and two timed runs each, HIP events on
+ *   `stream`), keeps the faster one for dimension d and returns the times in
+ *   ms_out[DPC_BACKEND_*] and the choice in *chosen (either may be NULL).
+ *   Arguments as for dpc_autotune.  Synchronises the stream.
+ */
+#define DPC_BACKEND_PRIORITY_TREE 0
+#define DPC_BACKEND_FENWICK 1
+DPC_API int dpc_set_dependent_backend(int32_t d, int32_t backend);
+DPC_API int32_t dpc_dependent_backend(int32_t d);
+DPC_API int dpc_autotune_dependent(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,
+                                   double delta_min, hipStream_t stream, double *ms_out, int32_t *chosen);
 
 /*
  * Diagnostics: copies the measurements of the calling thread's most recent

@@ -6,6 +6,7 @@ include/libdpc.h; this package is its thin Python binding.  See
 ``run`` take and return device tensors.
 """
 from ._binding import (  # noqa: F401
+    BACKENDS,
     Batch,
     DPCError,
     Instance,
@@ -18,16 +19,19 @@ from ._binding import (  # noqa: F401
     Server,
     WORK_FIELDS,
     autotune,
+    autotune_dependent,
     batch_run,
     cluster,
     cluster_sweep,
     density,
     density_sweep,
+    dependent_backend,
     dependent,
     last_stats,
     leaf_size,
     load,
     run,
+    set_dependent_backend,
     set_leaf_size,
     square_threshold,
     status_str,

@@ -17,6 +17,8 @@ OK, ERR_INVALID_ARG, ERR_RANGE, ERR_NOT_FOREST, ERR_OOM, ERR_HIP = range(6)
 SKIP_NOISE_DEPENDENTS = 1
 TIME_STAGES = 2
 COUNT_WORK = 4
+FENWICK_DEPENDENTS = 8
+BACKENDS = ("priority_tree", "fenwick")  # DPC_BACKEND_PRIORITY_TREE, DPC_BACKEND_FENWICK
 INF = (1 << 63) - 1
 STAGES = ("index", "density", "priority", "dependent", "labels")
 
@@ -25,7 +27,8 @@ EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_batch
             "dpc_cluster_sweep", "dpc_server_create",
             "dpc_server_submit", "dpc_server_poll", "dpc_server_wait", "dpc_server_get_stats",
             "dpc_server_destroy", "dpc_set_leaf_size", "dpc_leaf_size", "dpc_autotune", "dpc_plan_create",
-            "dpc_plan_launch", "dpc_plan_capture", "dpc_plan_status", "dpc_plan_destroy")
+            "dpc_plan_launch", "dpc_plan_capture", "dpc_plan_status", "dpc_plan_destroy",
+            "dpc_set_dependent_backend", "dpc_dependent_backend", "dpc_autotune_dependent")
 
 
 class Stats(ctypes.Structure):
@@ -133,6 +136,12 @@ def load():
     lib.dpc_plan_status.restype = ctypes.c_int
     lib.dpc_plan_destroy.argtypes = [P]
     lib.dpc_plan_destroy.restype = ctypes.c_int
+    lib.dpc_set_dependent_backend.argtypes = [i32, i32]
+    lib.dpc_set_dependent_backend.restype = ctypes.c_int
+    lib.dpc_dependent_backend.argtypes = [i32]
+    lib.dpc_dependent_backend.restype = ctypes.c_int32
+    lib.dpc_autotune_dependent.argtypes = [P, i64, i32, dbl, i32, dbl, P, ctypes.POINTER(dbl), ctypes.POINTER(i32)]
+    lib.dpc_autotune_dependent.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -249,11 +258,13 @@ def last_stats() -> dict:
 
 
 def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool = False, out=None,
-        stream=None, time_stages: bool = False, count_work: bool = False):
+        stream=None, time_stages: bool = False, count_work: bool = False, fenwick: bool = False):
     """(rho, dep, delta2, label) of the whole method on device points.
 
     time_stages / count_work record per-step GPU times / work counters of
-    this call for last_stats() (measurement only)."""
+    this call for last_stats() (measurement only).  fenwick finds the
+    dependent points with the Fenwick tree of k-d trees instead of the
+    priority-search k-d tree (same outputs)."""
     torch = _torch()
     n, d = _check_points(points)
     dev = points.device
@@ -264,7 +275,7 @@ def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool =
     delta2 = _out(out[2], n, torch.int64, dev)
     label = _out(out[3], n, torch.int32, dev)
     flags = (SKIP_NOISE_DEPENDENTS if skip_noise else 0) | (TIME_STAGES if time_stages else 0) \
-        | (COUNT_WORK if count_work else 0)
+        | (COUNT_WORK if count_work else 0) | (FENWICK_DEPENDENTS if fenwick else 0)
     st = load().dpc_run(_ptr(points), n, d, float(d_cut), int(rho_min), float(delta_min), flags, _ptr(rho),
                         _ptr(dep), _ptr(delta2), _ptr(label), _stream(stream))
     if st != OK:
@@ -522,3 +533,33 @@ def autotune(points, d_cut: float, rho_min: int, delta_min: float, stream=None) 
     if st != OK:
         raise DPCError(st, "dpc_autotune")
     return {"ms": {16: ms[0], 32: ms[1]}, "chosen": ch.value}
+
+
+def set_dependent_backend(d: int, backend: str) -> None:
+    """Dependent-point backend dpc_run uses for dimension d: "priority_tree"
+    or "fenwick" (same outputs)."""
+    if backend not in BACKENDS:
+        raise ValueError(f"backend must be one of {BACKENDS}")
+    st = load().dpc_set_dependent_backend(int(d), BACKENDS.index(backend))
+    if st != OK:
+        raise DPCError(st, "dpc_set_dependent_backend")
+
+
+def dependent_backend(d: int) -> str:
+    b = load().dpc_dependent_backend(int(d))
+    if b < 0:
+        raise DPCError(ERR_INVALID_ARG, "dpc_dependent_backend")
+    return BACKENDS[b]
+
+
+def autotune_dependent(points, d_cut: float, rho_min: int, delta_min: float, stream=None) -> dict:
+    """Times both dependent-point backends on this instance and keeps the
+    faster for its dimension; returns {"ms": {backend: t}, "chosen": backend}."""
+    n, d = _check_points(points)
+    ms = (ctypes.c_double * 2)()
+    ch = ctypes.c_int32()
+    st = load().dpc_autotune_dependent(_ptr(points), n, d, float(d_cut), int(rho_min), float(delta_min),
+                                       _stream(stream), ms, ctypes.byref(ch))
+    if st != OK:
+        raise DPCError(st, "dpc_autotune_dependent")
+    return {"ms": {BACKENDS[0]: ms[0], BACKENDS[1]: ms[1]}, "chosen": BACKENDS[ch.value]}

@@ -2,6 +2,8 @@
 // thresholds, workspace lifetime and the order of the steps.
 #include "dpc_internal.hpp"
 
+#include <atomic>
+
 #include <cmath>
 #include <limits>
 #include <mutex>
@@ -226,7 +228,7 @@ dpc_status make_job(const int32_t *points, int64_t n, int32_t d, double d_cut, i
 // The whole method on one group (instances of one dimension and one
 // arithmetic), every step once for all of them.
 dpc_status run_group(const std::vector<Job> &jobs, int d, Arith arith, RunRecorder *rec, int64_t *counters,
-                     Workspace &ws) {
+                     Workspace &ws, bool fenwick = false) {
     hipStream_t stream = ws.stream;
     Index ix;
     DPC_TRY(build_group(jobs, d, arith, leaf_log2(d), ws, ix));
@@ -237,10 +239,17 @@ dpc_status run_group(const std::vector<Job> &jobs, int d, Arith arith, RunRecord
     DPC_TRY(launch_density(ix, srho, counters, stream));
     if (rec)
         DPC_TRY(rec->mark(DPC_STAGE_DENSITY));
-    DPC_TRY(build_priority(srho, false, ws, ix));
-    if (rec)
-        DPC_TRY(rec->mark(DPC_STAGE_PRIORITY));
-    DPC_TRY(launch_dependent(ix, counters, stream));
+    if (fenwick && ix.count == 1) {
+        // the Fenwick tree of Algorithm 2 orders the points by priority itself
+        if (rec)
+            DPC_TRY(rec->mark(DPC_STAGE_PRIORITY));
+        DPC_TRY(fenwick_dependent(jobs[0], d, arith, ix.lsh, ws));
+    } else {
+        DPC_TRY(build_priority(srho, false, ws, ix));
+        if (rec)
+            DPC_TRY(rec->mark(DPC_STAGE_PRIORITY));
+        DPC_TRY(launch_dependent(ix, counters, stream));
+    }
     if (rec)
         DPC_TRY(rec->mark(DPC_STAGE_DEPENDENT));
     DPC_TRY(launch_group_labels(ix, ws));
@@ -318,6 +327,59 @@ dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int cou
     return (dpc_status)first_error;
 }
 
+
+namespace {
+
+// Dependent-point backend per dimension (DPC_BACKEND_*), read by dpc_run.
+std::atomic<int> g_backend[kMaxDim + 1] = {};
+
+// The whole method on one instance with the current settings: one warm-up
+// run, then the faster of two, timed with HIP events on the stream; the
+// outputs go to workspace.
+dpc_status time_choice(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
+                       bool fenwick, hipStream_t stream, float *best_ms) {
+    Job J;
+    int32_t *rho, *dep, *label;
+    int64_t *delta2;
+    Workspace ws(stream);
+    DPC_TRY(ws.alloc(&rho, (size_t)n));
+    DPC_TRY(ws.alloc(&dep, (size_t)n));
+    DPC_TRY(ws.alloc(&label, (size_t)n));
+    DPC_TRY(ws.alloc(&delta2, (size_t)n));
+    DPC_TRY(make_job(points, n, d, d_cut, rho_min, delta_min, 0, rho, dep, delta2, label, J));
+    hipEvent_t e0, e1;
+    DPC_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipGetLastError();
+        return DPC_ERR_HIP;
+    }
+    dpc_status st = DPC_OK;
+    for (int r = 0; r < 3 && st == DPC_OK; ++r) {
+        std::vector<Job> jobs{J};
+        Workspace run_ws(stream);
+        if (hipEventRecord(e0, stream) != hipSuccess)
+            st = DPC_ERR_HIP;
+        if (st == DPC_OK)
+            st = job_bounds(jobs, d, run_ws, nullptr);
+        if (st == DPC_OK)
+            st = run_group(jobs, d, job_arith(jobs[0], d), nullptr, nullptr, run_ws, fenwick);
+        if (st == DPC_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+            st = DPC_ERR_HIP;
+        float ms = 0.0f;
+        if (st == DPC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            st = DPC_ERR_HIP;
+        if (st == DPC_OK && r > 0 && (r == 1 || ms < *best_ms))
+            *best_ms = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != DPC_OK)
+        (void)hipGetLastError();
+    return st;
+}
+
+}  // namespace
 
 }  // namespace dpc
 
@@ -478,7 +540,7 @@ int dpc_cluster_sweep(int64_t n, const int32_t *rho, const int32_t *dep, const i
 
 int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
             uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2, int32_t *label, hipStream_t stream) {
-    const uint32_t known = DPC_SKIP_NOISE_DEPENDENTS | DPC_TIME_STAGES | DPC_COUNT_WORK;
+    const uint32_t known = DPC_SKIP_NOISE_DEPENDENTS | DPC_TIME_STAGES | DPC_COUNT_WORK | DPC_FENWICK_DEPENDENTS;
     if (flags & ~known)
         return DPC_ERR_INVALID_ARG;
     Job J;
@@ -496,7 +558,8 @@ int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t r
     }
     std::vector<Job> jobs{J};
     DPC_TRY(job_bounds(jobs, d, ws, nullptr));
-    DPC_TRY(run_group(jobs, d, job_arith(jobs[0], d), &rec, counters, ws));
+    const bool fenwick = (flags & DPC_FENWICK_DEPENDENTS) || g_backend[d].load(std::memory_order_relaxed) == DPC_BACKEND_FENWICK;
+    DPC_TRY(run_group(jobs, d, job_arith(jobs[0], d), &rec, counters, ws, fenwick));
     if (counters)
         DPC_TRY(rec.read_counters(counters));
     rec.commit(ws.bytes);
@@ -531,52 +594,16 @@ int32_t dpc_leaf_size(int32_t d) {
 
 int dpc_autotune(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
                  hipStream_t stream, double *ms_out, int32_t *chosen) {
-    Job J;
     if (bad_shape(n, d) || n == 0 || points == nullptr)
         return DPC_ERR_INVALID_ARG;
-    int32_t *rho, *dep, *label;
-    int64_t *delta2;
-    Workspace ws(stream);
-    DPC_TRY(ws.alloc(&rho, (size_t)n));
-    DPC_TRY(ws.alloc(&dep, (size_t)n));
-    DPC_TRY(ws.alloc(&label, (size_t)n));
-    DPC_TRY(ws.alloc(&delta2, (size_t)n));
-    DPC_TRY(make_job(points, n, d, d_cut, rho_min, delta_min, 0, rho, dep, delta2, label, J));
-    hipEvent_t e0, e1;
-    DPC_HIP(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        (void)hipGetLastError();
-        return DPC_ERR_HIP;
-    }
     const int before = leaf_log2(d);
-    dpc_status st = DPC_OK;
     float best_ms[2] = {0.0f, 0.0f};
+    dpc_status st = DPC_OK;
     for (int c = 0; c < 2 && st == DPC_OK; ++c) {
         set_leaf_log2(d, kMinLeafLog2 + c);
-        // one warm-up run, then the faster of two timed runs
-        for (int r = 0; r < 3 && st == DPC_OK; ++r) {
-            std::vector<Job> jobs{J};
-            Workspace run_ws(stream);
-            if (hipEventRecord(e0, stream) != hipSuccess)
-                st = DPC_ERR_HIP;
-            if (st == DPC_OK)
-                st = job_bounds(jobs, d, run_ws, nullptr);
-            if (st == DPC_OK)
-                st = run_group(jobs, d, job_arith(jobs[0], d), nullptr, nullptr, run_ws);
-            if (st == DPC_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-                st = DPC_ERR_HIP;
-            float ms = 0.0f;
-            if (st == DPC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-                st = DPC_ERR_HIP;
-            if (st == DPC_OK && r > 0 && (r == 1 || ms < best_ms[c]))
-                best_ms[c] = ms;
-        }
+        st = time_choice(points, n, d, d_cut, rho_min, delta_min, false, stream, &best_ms[c]);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (st != DPC_OK) {
-        (void)hipGetLastError();
         set_leaf_log2(d, before);
         return st;
     }
@@ -588,6 +615,38 @@ int dpc_autotune(const int32_t *points, int64_t n, int32_t d, double d_cut, int3
     }
     if (chosen)
         *chosen = 1 << pick;
+    return DPC_OK;
+}
+
+int dpc_set_dependent_backend(int32_t d, int32_t backend) {
+    if (d < 1 || d > kMaxDim || (backend != DPC_BACKEND_PRIORITY_TREE && backend != DPC_BACKEND_FENWICK))
+        return DPC_ERR_INVALID_ARG;
+    g_backend[d].store(backend, std::memory_order_relaxed);
+    return DPC_OK;
+}
+
+int32_t dpc_dependent_backend(int32_t d) {
+    if (d < 1 || d > kMaxDim)
+        return -1;
+    return g_backend[d].load(std::memory_order_relaxed);
+}
+
+int dpc_autotune_dependent(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,
+                           double delta_min, hipStream_t stream, double *ms_out, int32_t *chosen) {
+    if (bad_shape(n, d) || n == 0 || points == nullptr)
+        return DPC_ERR_INVALID_ARG;
+    float best_ms[2] = {0.0f, 0.0f};
+    for (int c = 0; c < 2; ++c)
+        DPC_TRY(time_choice(points, n, d, d_cut, rho_min, delta_min, c == DPC_BACKEND_FENWICK, stream, &best_ms[c]));
+    const int pick = best_ms[DPC_BACKEND_FENWICK] < best_ms[DPC_BACKEND_PRIORITY_TREE] ? DPC_BACKEND_FENWICK
+                                                                                     : DPC_BACKEND_PRIORITY_TREE;
+    g_backend[d].store(pick, std::memory_order_relaxed);
+    if (ms_out) {
+        ms_out[0] = best_ms[0];
+        ms_out[1] = best_ms[1];
+    }
+    if (chosen)
+        *chosen = pick;
     return DPC_OK;
 }
 

@@ -71,7 +71,8 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                                                         const uint64_t *__restrict__ skey,
                                                         const uint64_t *__restrict__ maxkey,
                                                         const uint64_t *__restrict__ split, Lo lo, int64_t n,
-                                                        int height, int32_t rho_min, const int32_t *__restrict__ sidx,
+                                                        int height, int32_t rho_min, int32_t rho_max,
+                                                        const int32_t *__restrict__ sidx,
                                                         int32_t *__restrict__ dep_out,
                                                         int64_t *__restrict__ delta2_out, int64_t *counters,
                                                         const Inst *__restrict__ inst,
@@ -87,6 +88,7 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
         n = I.n;
         height = I.height;
         rho_min = I.dep_rho_min;
+        rho_max = I.dep_rho_max;
         coords += I.P * D;
         box += I.N * 2 * D;
         skey += I.P;
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
         x[k] = coords[qq * D + k];
     const uint64_t kq = skey[qq];
     const int32_t rho_q = (int32_t)((uint32_t)(kq >> 32) ^ 0x80000000u);
-    const bool active = valid && rho_q >= rho_min;
+    const bool active = valid && rho_q >= rho_min && rho_q <= rho_max;
     // the wave's first query, relative to lo: the reference point that
     // decides which child of a node is searched first
     uint32_t ref[D];
@@ -262,7 +264,7 @@ dpc_status launch_typed(const Index &ix, int64_t *counters, hipStream_t s) {
 #define DPC_DEP_CASE(DD)                                                                                          \
     case DD:                                                                                                      \
         launch((k_dependent<C, DD, STATS, GROUP, LSH>), grid, block, 0, s, coords, box, ix.skey,     \
-                           ix.maxkey, ix.split, lo, I.n, I.height, I.dep_rho_min, ix.sidx, I.dep, I.delta2, counters, \
+                           ix.maxkey, ix.split, lo, I.n, I.height, I.dep_rho_min, I.dep_rho_max, ix.sidx, I.dep, I.delta2, counters, \
                            ix.inst, ix.tile_inst);                                                                 \
         break;
         DPC_DEP_CASE(1)

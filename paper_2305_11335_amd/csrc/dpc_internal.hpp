@@ -23,6 +23,7 @@
 #include <stdint.h>
 
 #include <functional>
+#include <limits>
 #include <vector>
 
 #include "../../include/libdpc.h"
@@ -62,6 +63,7 @@ struct Inst {
     int32_t M, R, limit, Tn;
     // dependent points and labels
     int32_t dep_rho_min;  // dependents of points below it are skipped
+    int32_t dep_rho_max;  // and of points above it
     int32_t rho_min;
     int64_t Td;
     // caller's arrays (input order)
@@ -78,6 +80,7 @@ struct Job {
     int64_t n = 0;
     int64_t T = 0;          // density threshold (unused by dpc_dependent)
     int32_t dep_rho_min = 0;
+    int32_t dep_rho_max = std::numeric_limits<int32_t>::max();
     int32_t rho_min = 0;
     int64_t Td = 0;
     int32_t *rho = nullptr;
@@ -207,6 +210,14 @@ __device__ inline __attribute__((address_space(1))) T *global_ptr(T *p) {
 
 // The instance that owns a tile, and the instance-local position of the
 // tile's first element.
+// Priority keys: the high word is rho with its sign bit flipped (so unsigned
+// order is signed order), the low word 2^32 - 1 - original index.  A larger
+// key means higher density, or equal density and a lower index: the priority
+// (rho, -index).  No real key is 0, which marks padding.
+__host__ __device__ inline uint64_t pack_key(int32_t rho, int32_t orig) {
+    return ((uint64_t)((uint32_t)rho ^ 0x80000000u) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)orig);
+}
+
 __device__ inline const Inst &inst_of_tile(const Inst *__restrict__ inst, const uint32_t *__restrict__ tile_inst,
                                            int64_t tile) {
     return inst[tile_inst ? tile_inst[tile] : 0u];
@@ -244,6 +255,12 @@ void set_leaf_log2(int d, int lsh);
 // Priority keys and per-node maxima; rho in sorted order (srho) or in each
 // instance's input order (rho_orig: use the instances' rho arrays).
 dpc_status build_priority(const int32_t *srho, bool rho_orig, Workspace &ws, Index &ix);
+// The per-node maximum keys above the leaf maxima already in ix.maxkey.
+dpc_status priority_levels(Index &ix, hipStream_t s);
+// Dependent points of one instance through a Fenwick tree of k-d trees
+// (Section 5, Algorithm 2), from the rho array the job holds (input order);
+// writes the job's dep and delta2.  Results equal launch_dependent's.
+dpc_status fenwick_dependent(const Job &J, int d, Arith arith, int lsh, Workspace &ws);
 
 // Allocates the group's descriptors (and tile table) and copies them to the
 // device (synchronising the stream).

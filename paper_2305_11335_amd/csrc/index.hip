@@ -164,14 +164,7 @@ __global__ __launch_bounds__(kThreads) void k_bounds_reduce(const Inst *__restri
 }
 
 // ---------------------------------------------------------------------------
-// priority keys: the high word is rho with its sign bit flipped (so unsigned
-// order is signed order), the low word 2^32 - 1 - original index.  A larger
-// key means higher density, or equal density and a lower index: the priority
-// (rho, -index).  No real key is 0, which marks padding.
-
-__device__ inline uint64_t pack_key(int32_t rho, int32_t orig) {
-    return ((uint64_t)((uint32_t)rho ^ 0x80000000u) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)orig);
-}
+// priority keys (pack_key) and the per-node maxima
 
 __device__ inline uint64_t shfl_xor_u64(uint64_t v, int o) {
     uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
@@ -505,6 +498,7 @@ dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, int lsh
         if (I.limit < 0)
             ix.intbox = false;
         I.dep_rho_min = J.dep_rho_min;
+        I.dep_rho_max = J.dep_rho_max;
         I.rho_min = J.rho_min;
         I.Td = J.Td;
         I.points = J.points;
@@ -548,6 +542,10 @@ dpc_status build_priority(const int32_t *srho, bool rho_orig, Workspace &ws, Ind
                        (uint64_t)0);
     launch(k_keys_leaf, dim3(blocks_for(ix.positions, kThreads)), dim3(kThreads), 0, s, ix.inst,
                        ix.tile_inst, srho, ix.sidx, ix.skey, ix.maxkey);
+    return priority_levels(ix, s);
+}
+
+dpc_status priority_levels(Index &ix, hipStream_t s) {
     if (ix.count == 1) {
         for (int depth = ix.host[0].height; depth > 0;) {
             const int lv = depth < 8 ? depth : 8;

@@ -34,7 +34,8 @@ def test_header_declares_the_interface():
                                   "dpc_autotune",
                                   "dpc_server_create", "dpc_server_submit", "dpc_server_poll", "dpc_server_wait",
                                   "dpc_server_get_stats", "dpc_server_destroy", "dpc_plan_create", "dpc_plan_launch",
-                                  "dpc_plan_capture", "dpc_plan_status", "dpc_plan_destroy"])
+                                  "dpc_plan_capture", "dpc_plan_status", "dpc_plan_destroy",
+                                  "dpc_set_dependent_backend", "dpc_dependent_backend", "dpc_autotune_dependent"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -120,7 +121,8 @@ def test_argument_errors_before_any_device_work():
     assert _call("dpc_run", fake, 5, 2, float("nan"), 0, 1.0, 0, fake, fake, fake, fake, NULL) == E
     assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 0, fake, fake, NULL, fake, NULL) == E
     assert _call("dpc_run", fake, 5, 0, 1.0, 0, 1.0, 0, fake, fake, fake, fake, NULL) == E
-    assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 8, fake, fake, fake, fake, NULL) == E
+    assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 16, fake, fake, fake, fake, NULL) == E
+    assert _call("dpc_run", fake, 5, 0, 1.0, 0, 1.0, 8, fake, fake, fake, fake, NULL) == E  # Fenwick flag, bad d
     assert dpc.load().dpc_last_stats(None) == E
     assert _call("dpc_batch_run", None, 3, 0, NULL) == E
     assert _call("dpc_batch_run", None, -1, 0, NULL) == E
@@ -253,3 +255,20 @@ def test_plan_argument_errors():
     assert lib.dpc_plan_capture(None, fake) == E
     assert lib.dpc_plan_status(None, None, ctypes.byref(st)) == E
     assert lib.dpc_plan_destroy(None) == E
+
+
+def test_dependent_backend_setting_is_host_only():
+    for d in range(1, 9):
+        assert dpc.dependent_backend(d) == "priority_tree"
+    dpc.set_dependent_backend(4, "fenwick")
+    assert dpc.dependent_backend(4) == "fenwick" and dpc.dependent_backend(3) == "priority_tree"
+    dpc.set_dependent_backend(4, "priority_tree")
+    lib = dpc.load()
+    E = dpc._binding.ERR_INVALID_ARG
+    assert lib.dpc_set_dependent_backend(0, 0) == E and lib.dpc_set_dependent_backend(9, 1) == E
+    assert lib.dpc_set_dependent_backend(2, 2) == E and lib.dpc_set_dependent_backend(2, -1) == E
+    assert lib.dpc_dependent_backend(0) == -1 and lib.dpc_dependent_backend(9) == -1
+    with pytest.raises(ValueError):
+        dpc.set_dependent_backend(2, "grid")
+    assert lib.dpc_autotune_dependent(None, 10, 2, 1.0, 0, 1.0, None, None, None) == E
+    assert lib.dpc_autotune_dependent(None, 0, 2, 1.0, 0, 1.0, None, None, None) == E

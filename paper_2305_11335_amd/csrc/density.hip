@@ -187,7 +187,8 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
     uint64_t n_pairs = 0, n_nodes = 0, n_contained = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
     // this wave's instance; positions, nodes and leaves below are its own
-    const int64_t g0 = wave_base(kThreads);
+    // XCD runs measured best: 16 workgroups in 2-D, 128 from 3-D on
+    const int64_t g0 = wave_base<(D <= 2 ? 16u : 128u)>(kThreads);
     const Inst &I = inst_of_tile(inst, tile_inst, g0 / kTile);
     const int64_t n = I.n;
     const int height = I.height;

@@ -22,6 +22,7 @@ namespace dpc {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr uint32_t kDepXcdRun = 128;  // XCD run length (workgroups), measured best in 2-D to 8-D
 
 struct Lo {
     int32_t v[kMaxDim];  // global minimum per axis
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
     __shared__ uint64_t s_key[kThreads / kWave][kMaxLeaf];
     uint64_t n_pairs = 0, n_nodes = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
-    int64_t q0 = wave_base(kThreads);
+    int64_t q0 = wave_base<kDepXcdRun>(kThreads);
     if (GROUP) {
         const Inst &I = inst_of_tile(inst, tile_inst, q0 / kTile);
         q0 -= I.P;
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
         if (GROUP) {
             // the output arrays are looked up only now, so that their
             // addresses do not hold scalar registers during the walk
-            const Inst &J = inst_of_tile(inst, tile_inst, wave_base(kThreads) / kTile);
+            const Inst &J = inst_of_tile(inst, tile_inst, wave_base<kDepXcdRun>(kThreads) / kTile);
             dep_out = J.dep;
             delta2_out = J.delta2;
         }

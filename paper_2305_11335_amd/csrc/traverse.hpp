@@ -78,11 +78,31 @@ __device__ inline C point_dist2(const C (&x)[D], const C *__restrict__ p) {
     return s;
 }
 
+// The workgroups of a launch go to the 8 XCDs in turn (workgroup i to XCD
+// i mod 8), and each XCD has an L2 of its own.  This maps workgroup i to the
+// chunk of work it takes so that each XCD takes runs of RUN consecutive
+// chunks: neighbouring queries walk the same nodes and leaves, which then
+// stay in one L2, while the runs still alternate between XCDs so that dense
+// regions are shared out.  A bijection of [0, nb) for any nb (the last,
+// partial round of runs keeps the plain order).
+template <uint32_t RUN>
+__device__ inline uint32_t xcd_chunk(uint32_t b, uint32_t nb) {
+    constexpr uint32_t kXcds = 8;
+    if (RUN <= 1)
+        return b;
+    const uint32_t full = nb - nb % (kXcds * RUN);
+    if (b >= full)
+        return b;
+    const uint32_t x = b % kXcds, r = b / kXcds;
+    return ((r / RUN) * kXcds + x) * RUN + r % RUN;
+}
+
 // First query position of this wavefront (a value the compiler knows is
 // uniform across the wave, so state derived from it stays scalar).
+template <uint32_t RUN>
 __device__ inline int64_t wave_base(int block_threads) {
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    return (int64_t)blockIdx.x * block_threads + (int64_t)w * kWave;
+    return (int64_t)xcd_chunk<RUN>(blockIdx.x, gridDim.x) * block_threads + (int64_t)w * kWave;
 }
 
 // First sorted position and number of points below node v at `depth` of a

@@ -62,6 +62,99 @@ __device__ inline void consider_batch(const C (&x)[D], const C (&q)[kB][D], cons
     }
 }
 
+#ifndef DPC_DEP_COOP
+#define DPC_DEP_COOP 1
+#endif
+// Leaves wanted by at most this many lanes of a wave go the cooperative way.
+constexpr int kCoopMax = 32;
+
+template <typename C>
+__device__ inline C shfl_xor_c(C v, int off) {
+    static_assert(sizeof(C) == 8, "64-bit coordinates");
+    uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __shfl_xor((uint32_t)b, off, kWave), hi = __shfl_xor((uint32_t)(b >> 32), off, kWave);
+    return __builtin_bit_cast(C, ((uint64_t)hi << 32) | lo);
+}
+
+// A leaf that few lanes of the wave want.  Looping each of those lanes over
+// the leaf's points would leave most lanes idle, so the work is turned
+// around: lanes 0-31 and 32-63 each hold the leaf's points (one per lane),
+// the wanting lanes publish their query, current best and key in an LDS slot
+// each, and every step tests two queries against all points at once.  Only
+// when some point is a candidate at most as near as a query's best does the
+// half-wave reduce to the lexicographic minimum of (D^2, index) and update
+// that query's slot.  Same result as the per-lane loop.
+template <typename C, int D, bool STATS>
+__device__ inline void leaf_coop(const C *__restrict__ coords, const uint64_t *__restrict__ skey, int64_t start,
+                                 int count, uint64_t wm, bool want, const C (&x)[D], uint64_t kq, C &best,
+                                 uint32_t &best_low, C *__restrict__ sq, uint64_t *__restrict__ sqk,
+                                 C *__restrict__ sqb, uint32_t *__restrict__ sql, uint64_t &n_pairs) {
+    const int lane = __lane_id();
+    const int half = lane >> 5;
+    const int pl = lane & 31;
+    const bool has = pl < count;
+    const int64_t pp = start + (has ? pl : 0);
+    C px[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        px[k] = coords[pp * D + k];
+    const uint64_t pk = has ? skey[pp] : 0ull;  // 0: above no query's key
+    const int mine = __popcll(wm & ((1ull << lane) - 1ull));
+    if (want) {
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            sq[mine * D + k] = x[k];
+        sqk[mine] = kq;
+        sqb[mine] = best;
+        sql[mine] = best_low;
+    }
+    wave_lds_sync();
+    const int nq = __popcll(wm);
+    for (int r0 = 0; r0 < nq; r0 += 2) {
+        const int r = r0 + half;
+        const bool live = r < nq;
+        const int rr = live ? r : r0;
+        C qx[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            qx[k] = sq[rr * D + k];
+        const uint64_t qk = sqk[rr];
+        const C qb = sqb[rr];
+        const C s = dist2<C, D>(px, qx);
+        const bool cand = live && has && pk > qk;
+        if (STATS)
+            n_pairs += cand ? 1u : 0u;
+        const bool hit = cand && s <= qb;
+        const uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
+        if (hm != 0) {
+            C hs = hit ? s : std::numeric_limits<C>::max();
+            uint32_t hl = hit ? (uint32_t)pk : 0u;
+#pragma unroll
+            for (int off = 16; off > 0; off >>= 1) {
+                const C os = shfl_xor_c<C>(hs, off);
+                const uint32_t ol = __shfl_xor(hl, off, kWave);
+                const bool b = (os < hs) | ((os == hs) & (ol > hl));
+                hs = b ? os : hs;
+                hl = b ? ol : hl;
+            }
+            const bool any = ((hm >> (32 * half)) & 0xFFFFFFFFull) != 0;
+            if (pl == 0 && live && any) {
+                const uint32_t ql = sql[rr];
+                if ((hs < qb) | ((hs == qb) & (hl > ql))) {
+                    sqb[rr] = hs;
+                    sql[rr] = hl;
+                }
+            }
+        }
+    }
+    wave_lds_sync();
+    if (want) {
+        best = sqb[mine];
+        best_low = sql[mine];
+    }
+    wave_lds_sync();  // the slots are written again at the next leaf
+}
+
 // GROUP = false: one instance, whose arrays and parameters are the kernel's
 // arguments.  GROUP = true: each wave finds its instance from its tile; the
 // arguments are the group's arrays and the rest is read from the
@@ -80,6 +173,11 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                                                         const uint32_t *__restrict__ tile_inst) {
     __shared__ C s_pts[kThreads / kWave][kMaxLeaf * D];
     __shared__ uint64_t s_key[kThreads / kWave][kMaxLeaf];
+    // query slots of the cooperative leaf path
+    __shared__ C s_qx[DPC_DEP_COOP ? kThreads / kWave : 1][kCoopMax * D];
+    __shared__ uint64_t s_qk[DPC_DEP_COOP ? kThreads / kWave : 1][kCoopMax];
+    __shared__ C s_qb[DPC_DEP_COOP ? kThreads / kWave : 1][kCoopMax];
+    __shared__ uint32_t s_ql[DPC_DEP_COOP ? kThreads / kWave : 1][kCoopMax];
     uint64_t n_pairs = 0, n_nodes = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
     int64_t q0 = wave_base<kDepXcdRun>(kThreads);
@@ -146,9 +244,15 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
             if (STATS)
                 n_nodes += higher ? 1u : 0u;
             if (v >= first_leaf) {
-                if (STATS && __ballot(want) != 0)
+                const uint64_t wm = __builtin_amdgcn_ballot_w64(want);
+                if (STATS && wm != 0)
                     w_points += (uint64_t)count;
-                if (__ballot(want) != 0) {
+                if (DPC_DEP_COOP && wm != 0 && __popcll(wm) <= kCoopMax) {
+                    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+                    leaf_coop<C, D, STATS>(coords, skey, start, (int)count, wm, want, x, kq, best, best_low,
+                                           s_qx[DPC_DEP_COOP ? w : 0], s_qk[DPC_DEP_COOP ? w : 0],
+                                           s_qb[DPC_DEP_COOP ? w : 0], s_ql[DPC_DEP_COOP ? w : 0], n_pairs);
+                } else if (wm != 0) {
                     // the wave stages the leaf in its LDS slot (one coalesced
                     // load), then the lanes that want it read every point
                     // from there (same address for all lanes: a broadcast)

@@ -138,6 +138,49 @@ __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint
 
 __device__ inline int32_t clamp_i32(int32_t v, int32_t lo, int32_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Leaves partial to at most this many lanes of a wave are counted the
+// cooperative way, from three dimensions on (measured best: 16 lanes up to
+// 4-D, 32 above).
+constexpr int kDenCoopMax = 32;  // the most any dimension uses
+template <int D>
+constexpr int den_coop_max() {
+    return D <= 4 ? 16 : 32;
+}
+
+// Count of one leaf for the lanes in pm (the leaf is partial to them), the
+// cooperative way: each group of leaf-size lanes holds the leaf's points
+// (one per lane), the lanes in pm publish their query in an LDS slot each,
+// and every step tests one query per group against all points; the group's
+// hits are one population count, added by the query's own lane.  P holds the
+// point (a packed word set or coordinates), Q a query, and within(P, Q) is
+// the exact test.
+template <int LSH, typename P, typename Q, typename F>
+__device__ inline int32_t coop_count(uint64_t pm, bool partial, const P &pt, bool has, const Q &mine_q,
+                                     Q *__restrict__ slots, F within) {
+    constexpr int kL = 1 << LSH, kG = kWave / kL;
+    const int lane = __lane_id();
+    const int grp = lane >> LSH;
+    const int mine = __popcll(pm & ((1ull << lane) - 1ull));
+    if (partial)
+        slots[mine] = mine_q;
+    wave_lds_sync();
+    const int nq = __popcll(pm);
+    int32_t c = 0;
+    for (int r0 = 0; r0 < nq; r0 += kG) {
+        const int r = r0 + grp;
+        const bool live = r < nq;
+        const Q q = slots[live ? r : r0];
+        const uint64_t m = __builtin_amdgcn_ballot_w64(live && has && within(pt, q));
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+            const int hits = __popcll((m >> (g * kL)) & (kL == 64 ? ~0ull : ((1ull << kL) - 1ull)));
+            c += (partial && mine == r0 + g) ? hits : 0;
+        }
+    }
+    wave_lds_sync();  // the slots are written again at the next leaf
+    return c;
+}
+
 // Nearest and farthest squared distance from x to a box (both relative to
 // lo), with every per-axis gap clamped to M: a gap of M or more already puts
 // the distance above T, and a clamped sum is then still at least M^2 > T, so
@@ -183,7 +226,8 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
     constexpr bool kPacked = std::is_same<C, double>::value;
     constexpr int W = (D + 1) / 2;
     // one staged leaf per wave: D 8-byte coordinates or W packed words per point
-    __shared__ uint64_t s_leaf[kThreads / kWave][D >= 3 ? kMaxLeaf * D : 1];
+    // (also the query slots of the cooperative count: at most kDenCoopMax)
+    __shared__ uint64_t s_leaf[kThreads / kWave][D >= 3 ? (kMaxLeaf > kDenCoopMax ? kMaxLeaf : kDenCoopMax) * D : 1];
     uint64_t n_pairs = 0, n_nodes = 0, n_contained = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
     // this wave's instance; positions, nodes and leaves below are its own
@@ -282,6 +326,62 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
             n_pairs += (uint64_t)count;
         const uint32_t c = leaf - first_leaf;
         const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+        if constexpr (kStage) {
+            const uint64_t pm = __builtin_amdgcn_ballot_w64(partial);
+            if (__popcll(pm) <= den_coop_max<D>()) {
+                constexpr int kL = 1 << lsh;
+                const int pl = lane & (kL - 1);
+                const bool has = pl < count;
+                const int64_t pp = start + (has ? pl : 0);
+                if constexpr (kPacked) {
+                    if ((int32_t)nw.ext[c] <= nw.limit) {
+                        struct PW {
+                            uint32_t v[W];
+                        };
+                        PW pt, qw;
+#pragma unroll
+                        for (int k = 0; k < W; ++k)
+                            pt.v[k] = nw.pack[pp * W + k];
+#pragma unroll
+                        for (int k = 0; k < W; ++k) {
+                            const int32_t a =
+                                clamp_i32(xi[2 * k] - (int32_t)nw.org[(size_t)c * D + 2 * k], -nw.M, nw.R);
+                            const int32_t b =
+                                2 * k + 1 < D
+                                    ? clamp_i32(xi[2 * k + 1] - (int32_t)nw.org[(size_t)c * D + 2 * k + 1], -nw.M,
+                                                nw.R)
+                                    : 0;
+                            qw.v[k] = ((uint32_t)a & 0xFFFFu) | ((uint32_t)b << 16);
+                        }
+                        const int32_t base = -(nw.T + 1);
+                        cnt += coop_count<lsh>(pm, partial, pt, has, qw, reinterpret_cast<PW *>(s_leaf[w]),
+                                               [&](const PW &a, const PW &b) {
+                                                   int32_t acc = base;
+#pragma unroll
+                                                   for (int k = 0; k < W; ++k) {
+                                                       const short2_t dv = __builtin_bit_cast(short2_t, b.v[k]) -
+                                                                           __builtin_bit_cast(short2_t, a.v[k]);
+                                                       acc = __builtin_amdgcn_sdot2(dv, dv, acc, true);
+                                                   }
+                                                   return acc < 0;
+                                               });
+                        return;
+                    }
+                }
+                struct PC {
+                    C v[D];
+                };
+                PC pt, qx;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    pt.v[k] = coords[pp * D + k];
+                    qx.v[k] = x[k];
+                }
+                cnt += coop_count<lsh>(pm, partial, pt, has, qx, reinterpret_cast<PC *>(s_leaf[w]),
+                                       [&](const PC &a, const PC &b) { return dist2<C, D>(a.v, b.v) <= T; });
+                return;
+            }
+        }
         if constexpr (kPacked) {
             const uint32_t *pk = nw.pack + start * W;
             if constexpr (kStage) {

@@ -62,11 +62,12 @@ __device__ inline void consider_batch(const C (&x)[D], const C (&q)[kB][D], cons
     }
 }
 
-#ifndef DPC_DEP_COOP
-#define DPC_DEP_COOP 1
-#endif
-// Leaves wanted by at most this many lanes of a wave go the cooperative way.
-constexpr int kCoopMax = 32;
+// Leaves wanted by at most this many lanes of a wave go the cooperative way
+// (measured: up to 32 of 64 lanes in 1-D to 4-D, every leaf from 5-D on).
+template <int D>
+constexpr int coop_max() {
+    return D <= 4 ? 32 : kWave;
+}
 
 template <typename C>
 __device__ inline C shfl_xor_c(C v, int off) {
@@ -78,20 +79,24 @@ __device__ inline C shfl_xor_c(C v, int off) {
 
 // A leaf that few lanes of the wave want.  Looping each of those lanes over
 // the leaf's points would leave most lanes idle, so the work is turned
-// around: lanes 0-31 and 32-63 each hold the leaf's points (one per lane),
-// the wanting lanes publish their query, current best and key in an LDS slot
-// each, and every step tests two queries against all points at once.  Only
-// when some point is a candidate at most as near as a query's best does the
-// half-wave reduce to the lexicographic minimum of (D^2, index) and update
-// that query's slot.  Same result as the per-lane loop.
-template <typename C, int D, bool STATS>
+// around: every group of leaf-size lanes holds the leaf's points (one per
+// lane), the wanting lanes publish their query, current best and key in an
+// LDS slot each, and every step tests one query per group against all
+// points at once.  Only when some point is a candidate at most as near as a
+// query's best does the group reduce to the lexicographic minimum of
+// (D^2, index) and update that query's slot.  Same result as the per-lane
+// loop.
+template <typename C, int D, bool STATS, int LSH>
 __device__ inline void leaf_coop(const C *__restrict__ coords, const uint64_t *__restrict__ skey, int64_t start,
                                  int count, uint64_t wm, bool want, const C (&x)[D], uint64_t kq, C &best,
                                  uint32_t &best_low, C *__restrict__ sq, uint64_t *__restrict__ sqk,
                                  C *__restrict__ sqb, uint32_t *__restrict__ sql, uint64_t &n_pairs) {
+    // kG groups of 2^LSH lanes, each holding the leaf's points, take kG
+    // queries per step
+    constexpr int kL = 1 << LSH, kG = kWave / kL;
     const int lane = __lane_id();
-    const int half = lane >> 5;
-    const int pl = lane & 31;
+    const int grp = lane >> LSH;
+    const int pl = lane & (kL - 1);
     const bool has = pl < count;
     const int64_t pp = start + (has ? pl : 0);
     C px[D];
@@ -110,8 +115,8 @@ __device__ inline void leaf_coop(const C *__restrict__ coords, const uint64_t *_
     }
     wave_lds_sync();
     const int nq = __popcll(wm);
-    for (int r0 = 0; r0 < nq; r0 += 2) {
-        const int r = r0 + half;
+    for (int r0 = 0; r0 < nq; r0 += kG) {
+        const int r = r0 + grp;
         const bool live = r < nq;
         const int rr = live ? r : r0;
         C qx[D];
@@ -130,14 +135,14 @@ __device__ inline void leaf_coop(const C *__restrict__ coords, const uint64_t *_
             C hs = hit ? s : std::numeric_limits<C>::max();
             uint32_t hl = hit ? (uint32_t)pk : 0u;
 #pragma unroll
-            for (int off = 16; off > 0; off >>= 1) {
+            for (int off = kL / 2; off > 0; off >>= 1) {
                 const C os = shfl_xor_c<C>(hs, off);
                 const uint32_t ol = __shfl_xor(hl, off, kWave);
                 const bool b = (os < hs) | ((os == hs) & (ol > hl));
                 hs = b ? os : hs;
                 hl = b ? ol : hl;
             }
-            const bool any = ((hm >> (32 * half)) & 0xFFFFFFFFull) != 0;
+            const bool any = ((hm >> (kL * grp)) & ((1ull << kL) - 1ull)) != 0;
             if (pl == 0 && live && any) {
                 const uint32_t ql = sql[rr];
                 if ((hs < qb) | ((hs == qb) & (hl > ql))) {
@@ -174,10 +179,11 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
     __shared__ C s_pts[kThreads / kWave][kMaxLeaf * D];
     __shared__ uint64_t s_key[kThreads / kWave][kMaxLeaf];
     // query slots of the cooperative leaf path
-    __shared__ C s_qx[DPC_DEP_COOP ? kThreads / kWave : 1][kCoopMax * D];
-    __shared__ uint64_t s_qk[DPC_DEP_COOP ? kThreads / kWave : 1][kCoopMax];
-    __shared__ C s_qb[DPC_DEP_COOP ? kThreads / kWave : 1][kCoopMax];
-    __shared__ uint32_t s_ql[DPC_DEP_COOP ? kThreads / kWave : 1][kCoopMax];
+    constexpr int kCoopMax = coop_max<D>();
+    __shared__ C s_qx[kThreads / kWave][kCoopMax * D];
+    __shared__ uint64_t s_qk[kThreads / kWave][kCoopMax];
+    __shared__ C s_qb[kThreads / kWave][kCoopMax];
+    __shared__ uint32_t s_ql[kThreads / kWave][kCoopMax];
     uint64_t n_pairs = 0, n_nodes = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
     int64_t q0 = wave_base<kDepXcdRun>(kThreads);
@@ -247,12 +253,11 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                 const uint64_t wm = __builtin_amdgcn_ballot_w64(want);
                 if (STATS && wm != 0)
                     w_points += (uint64_t)count;
-                if (DPC_DEP_COOP && wm != 0 && __popcll(wm) <= kCoopMax) {
+                if (wm != 0 && (kCoopMax == kWave || __popcll(wm) <= kCoopMax)) {
                     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-                    leaf_coop<C, D, STATS>(coords, skey, start, (int)count, wm, want, x, kq, best, best_low,
-                                           s_qx[DPC_DEP_COOP ? w : 0], s_qk[DPC_DEP_COOP ? w : 0],
-                                           s_qb[DPC_DEP_COOP ? w : 0], s_ql[DPC_DEP_COOP ? w : 0], n_pairs);
-                } else if (wm != 0) {
+                    leaf_coop<C, D, STATS, LSH>(coords, skey, start, (int)count, wm, want, x, kq, best, best_low,
+                                                s_qx[w], s_qk[w], s_qb[w], s_ql[w], n_pairs);
+                } else if (kCoopMax < kWave && wm != 0) {
                     // the wave stages the leaf in its LDS slot (one coalesced
                     // load), then the lanes that want it read every point
                     // from there (same address for all lanes: a broadcast)

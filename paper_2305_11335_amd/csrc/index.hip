@@ -407,7 +407,12 @@ void density_params(Inst &I, int64_t T, int d) {
 // 3-D and 8-D, so it is the default (dpc_autotune measures an instance).
 // Any choice gives the same outputs.
 namespace {
-std::atomic<int> g_leaf_log2[kMaxDim + 1] = {5, 5, 5, 5, 5, 5, 5, 5, 5};
+#ifndef DPC_DEFAULT_LSH
+#define DPC_DEFAULT_LSH 5
+#endif
+std::atomic<int> g_leaf_log2[kMaxDim + 1] = {DPC_DEFAULT_LSH, DPC_DEFAULT_LSH, DPC_DEFAULT_LSH,
+                                             DPC_DEFAULT_LSH, DPC_DEFAULT_LSH, DPC_DEFAULT_LSH,
+                                             DPC_DEFAULT_LSH, DPC_DEFAULT_LSH, DPC_DEFAULT_LSH};
 }  // namespace
 
 int leaf_log2(int d) { return d >= 1 && d <= kMaxDim ? g_leaf_log2[d].load(std::memory_order_relaxed) : kMaxLeafLog2; }

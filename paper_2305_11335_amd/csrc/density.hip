@@ -139,12 +139,12 @@ __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint
 __device__ inline int32_t clamp_i32(int32_t v, int32_t lo, int32_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Leaves partial to at most this many lanes of a wave are counted the
-// cooperative way, from three dimensions on (measured best: 16 lanes up to
-// 4-D, 32 above).
+// cooperative way (measured best: 8 lanes up to 2-D, 16 up to 4-D, 32
+// above).
 constexpr int kDenCoopMax = 32;  // the most any dimension uses
 template <int D>
 constexpr int den_coop_max() {
-    return D <= 4 ? 16 : 32;
+    return D <= 2 ? 8 : (D <= 4 ? 16 : 32);
 }
 
 // Count of one leaf for the lanes in pm (the leaf is partial to them), the
@@ -227,7 +227,9 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
     constexpr int W = (D + 1) / 2;
     // one staged leaf per wave: D 8-byte coordinates or W packed words per point
     // (also the query slots of the cooperative count: at most kDenCoopMax)
-    __shared__ uint64_t s_leaf[kThreads / kWave][D >= 3 ? (kMaxLeaf > kDenCoopMax ? kMaxLeaf : kDenCoopMax) * D : 1];
+    __shared__ uint64_t s_leaf[kThreads / kWave]
+                              [D >= 3 ? (kMaxLeaf > kDenCoopMax ? kMaxLeaf : kDenCoopMax) * D
+                                      : (den_coop_max<D>() > 0 ? den_coop_max<D>() * D : 1)];
     uint64_t n_pairs = 0, n_nodes = 0, n_contained = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
     // this wave's instance; positions, nodes and leaves below are its own
@@ -326,7 +328,7 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
             n_pairs += (uint64_t)count;
         const uint32_t c = leaf - first_leaf;
         const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-        if constexpr (kStage) {
+        if constexpr (den_coop_max<D>() > 0) {
             const uint64_t pm = __builtin_amdgcn_ballot_w64(partial);
             if (__popcll(pm) <= den_coop_max<D>()) {
                 constexpr int kL = 1 << lsh;

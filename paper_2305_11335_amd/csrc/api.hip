@@ -2,11 +2,13 @@
 // thresholds, workspace lifetime and the order of the steps.
 #include "dpc_internal.hpp"
 
+#include <algorithm>
 #include <atomic>
 
 #include <cmath>
 #include <limits>
 #include <mutex>
+#include <thread>
 
 namespace dpc {
 
@@ -269,9 +271,57 @@ dpc_status check_instance(const dpc_instance &q, uint32_t flags) {
 // DPC_SKIP_NOISE_DEPENDENTS), grouped by dimension and arithmetic; sets each
 // record's status.  peak_bytes (optional): the largest workspace held at
 // once.
+namespace {
+
+// One dimension's instances of a batch: bounds, then one group per
+// arithmetic.  Sets the range errors of its instances; *range_error tells
+// whether there was one.
+dpc_status run_dimension(int d, const std::vector<int> &ids, const std::vector<Job> &all, dpc_instance *instances,
+                         hipStream_t stream, size_t *peak, bool *range_error) {
+    *peak = 0;
+    *range_error = false;
+    std::vector<Job> jobs;
+    for (int i : ids)
+        jobs.push_back(all[i]);
+    std::vector<int> bad;
+    {
+        Workspace ws(stream);
+        const dpc_status st = job_bounds(jobs, d, ws, &bad);
+        *peak = ws.bytes > *peak ? ws.bytes : *peak;
+        if (st != DPC_OK && st != DPC_ERR_RANGE)
+            return st;
+    }
+    for (int b : bad) {
+        instances[ids[b]].status = DPC_ERR_RANGE;
+        *range_error = true;
+    }
+    // one group per arithmetic
+    for (int a = 0; a < 2; ++a) {
+        const Arith arith = a == 0 ? Arith::F64 : Arith::I64;
+        std::vector<Job> group;
+        for (size_t k = 0; k < jobs.size(); ++k) {
+            if (instances[ids[k]].status != DPC_OK || job_arith(jobs[k], d) != arith)
+                continue;
+            group.push_back(jobs[k]);
+        }
+        // largest instances first: the dispatcher starts their waves
+        // first, so the group does not end on one large instance's tail
+        std::stable_sort(group.begin(), group.end(), [](const Job &x, const Job &y) { return x.n > y.n; });
+        if (!group.empty()) {
+            Workspace ws(stream);
+            const dpc_status st = run_group(group, d, arith, nullptr, nullptr, ws);
+            *peak = ws.bytes > *peak ? ws.bytes : *peak;
+            if (st != DPC_OK)
+                return st;
+        }
+    }
+    return DPC_OK;
+}
+
+}  // namespace
+
 dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int count, hipStream_t stream,
                          size_t *peak_bytes) {
-    size_t peak = 0;
     // checks, then groups by dimension
     std::vector<std::vector<int>> by_d(kMaxDim + 1);
     std::vector<Job> all(count);
@@ -285,45 +335,83 @@ dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int cou
         if (q.status != DPC_OK && first_error == DPC_OK)
             first_error = q.status;
     }
-    for (int d = 1; d <= kMaxDim; ++d) {
-        if (by_d[d].empty())
-            continue;
-        std::vector<Job> jobs;
-        for (int i : by_d[d])
-            jobs.push_back(all[i]);
-        std::vector<int> bad;
-        {
-            Workspace ws(stream);
-            const dpc_status st = job_bounds(jobs, d, ws, &bad);
-            peak = ws.bytes > peak ? ws.bytes : peak;
-            if (st != DPC_OK && st != DPC_ERR_RANGE)
-                return st;
+    std::vector<int> dims;
+    for (int d = 1; d <= kMaxDim; ++d)
+        if (!by_d[d].empty())
+            dims.push_back(d);
+    std::vector<dpc_status> st(dims.size(), DPC_OK);
+    std::vector<size_t> peak(dims.size(), 0);
+    std::vector<char> range(dims.size(), 0);
+    if (dims.size() <= 1) {
+        for (size_t k = 0; k < dims.size(); ++k) {
+            bool r = false;
+            st[k] = run_dimension(dims[k], by_d[dims[k]], all, instances, stream, &peak[k], &r);
+            range[k] = r;
         }
-        for (int b : bad) {
-            instances[by_d[d][b]].status = DPC_ERR_RANGE;
-            if (first_error == DPC_OK)
-                first_error = DPC_ERR_RANGE;
+    } else {
+        // several dimensions: each on a stream and host thread of its own,
+        // so that one group's host waits and short launches overlap another
+        // group's kernels.  The streams start after the caller's prior work
+        // and the caller's stream waits for all of them.
+        int dev = 0;
+        DPC_HIP(hipGetDevice(&dev));
+        hipEvent_t start_ev;
+        DPC_HIP(hipEventCreateWithFlags(&start_ev, hipEventDisableTiming));
+        std::vector<hipStream_t> streams(dims.size(), nullptr);
+        std::vector<hipEvent_t> done(dims.size(), nullptr);
+        dpc_status setup = hipEventRecord(start_ev, stream) == hipSuccess ? DPC_OK : DPC_ERR_HIP;
+        for (size_t k = 0; k < dims.size() && setup == DPC_OK; ++k) {
+            if (hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&done[k], hipEventDisableTiming) != hipSuccess ||
+                hipStreamWaitEvent(streams[k], start_ev, 0) != hipSuccess)
+                setup = DPC_ERR_HIP;
         }
-        // one group per arithmetic
-        for (int a = 0; a < 2; ++a) {
-            const Arith arith = a == 0 ? Arith::F64 : Arith::I64;
-            std::vector<Job> group;
-            for (size_t k = 0; k < jobs.size(); ++k) {
-                if (instances[by_d[d][k]].status != DPC_OK || job_arith(jobs[k], d) != arith)
-                    continue;
-                group.push_back(jobs[k]);
+        if (setup == DPC_OK) {
+            std::vector<std::thread> workers;
+            for (size_t k = 0; k < dims.size(); ++k) {
+                workers.emplace_back([&, k]() {
+                    if (hipSetDevice(dev) != hipSuccess) {
+                        st[k] = DPC_ERR_HIP;
+                        return;
+                    }
+                    bool r = false;
+                    st[k] = run_dimension(dims[k], by_d[dims[k]], all, instances, streams[k], &peak[k], &r);
+                    range[k] = r;
+                    if (hipEventRecord(done[k], streams[k]) != hipSuccess && st[k] == DPC_OK)
+                        st[k] = DPC_ERR_HIP;
+                });
             }
-            if (!group.empty()) {
-                Workspace ws(stream);
-                const dpc_status st = run_group(group, d, arith, nullptr, nullptr, ws);
-                peak = ws.bytes > peak ? ws.bytes : peak;
-                if (st != DPC_OK)
-                    return st;
-            }
+            for (auto &t : workers)
+                t.join();
+            for (size_t k = 0; k < dims.size(); ++k)
+                if (hipStreamWaitEvent(stream, done[k], 0) != hipSuccess && st[k] == DPC_OK)
+                    st[k] = DPC_ERR_HIP;
+        } else {
+            (void)hipGetLastError();
         }
+        for (size_t k = 0; k < dims.size(); ++k) {
+            if (done[k])
+                (void)hipEventDestroy(done[k]);
+            if (streams[k])
+                (void)hipStreamDestroy(streams[k]);  // released once its work is done
+        }
+        (void)hipEventDestroy(start_ev);
+        if (setup != DPC_OK)
+            return setup;
+    }
+    size_t total = 0;
+    for (size_t k = 0; k < dims.size(); ++k) {
+        if (st[k] != DPC_OK)
+            return st[k];
+        if (range[k] && first_error == DPC_OK)
+            first_error = DPC_ERR_RANGE;
+        // concurrent dimensions hold their workspaces at the same time
+        total += dims.size() > 1 ? peak[k] : 0;
+        if (dims.size() == 1)
+            total = peak[k];
     }
     if (peak_bytes)
-        *peak_bytes = peak;
+        *peak_bytes = total;
     return (dpc_status)first_error;
 }
 

@@ -119,3 +119,22 @@ def test_batch_full_workload():
         p, dc, rm, dm = probs[k]
         say("oracle check", k, p.shape)
         same(got[k], oracle.run(p, dc, rm, dm), f"instance {k} against the oracle")
+
+
+def test_batch_orders_with_the_callers_stream():
+    """Several dimensions run on library streams: inputs written and outputs
+    read by work queued on the caller's stream, with no host wait between."""
+    probs = [(datagen.clustered_small(40 + d, 20000, d, span=1 << 16), 900.0 * d, 2, 3600.0 * d) for d in (2, 3, 5)]
+    src = [dev(p) for p, *_ in probs]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pts = [torch.empty_like(x) for x in src]
+        for a, b in zip(pts, src):
+            a.copy_(b)
+        outs, st = dpc.batch_run([(p, dc, rm, dm) for p, (_, dc, rm, dm) in zip(pts, probs)], stream=s, check=False)
+        copies = [[t.clone() for t in o] for o in outs]
+    s.synchronize()
+    assert st == [0, 0, 0]
+    for k, (p, dc, rm, dm) in enumerate(probs):
+        same([t.cpu().numpy() for t in copies[k]], oracle.run(p, dc, rm, dm), f"instance {k} d={p.shape[1]}")

@@ -13,7 +13,8 @@
 // every point once; near candidates are met first, so the distance bounds
 // are tight by the time the large subtrees near the root are tested.  Inside
 // a subtree the nearer child (for the first lane that still needs the node)
-// is visited first.
+// is visited first.  A leaf that few lanes need is searched cooperatively
+// (leaf_coop), one that many need by each of those lanes in turn.
 #include "traverse.hpp"
 
 #include <limits>

@@ -337,6 +337,38 @@ def fenwick(torch, dpc, inst, P, want, runs: int = 3) -> dict:
             "outputs_identical_to_priority_tree": bool(same)}
 
 
+def transfers(torch, inst, ms_step: float, reps: int = 5) -> dict:
+    """Host-device copies around one step (context only: the library takes
+    device pointers, so they are not part of `value`): the points in from
+    pinned host memory, the four outputs back to pinned host memory."""
+    import numpy as np
+
+    n, d = inst.n, inst.d
+    h_pts = torch.empty((n, d), dtype=torch.int32, pin_memory=True)
+    h_pts.copy_(torch.from_numpy(np.ascontiguousarray(inst.points)))
+    d_pts = torch.empty((n, d), dtype=torch.int32, device="cuda:0")
+    d_out = [torch.empty(n, dtype=t, device="cuda:0") for t in (torch.int32, torch.int32, torch.int64, torch.int32)]
+    h_out = [torch.empty(n, dtype=t.dtype, pin_memory=True) for t in d_out]
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, (time.perf_counter() - t0) * 1000.0)
+        return best
+
+    h2d = timed(lambda: d_pts.copy_(h_pts, non_blocking=True))
+    d2h = timed(lambda: [h.copy_(t, non_blocking=True) for h, t in zip(h_out, d_out)])
+    in_b = n * d * 4
+    out_b = n * (4 + 4 + 8 + 4)
+    return {"h2d_ms": h2d, "h2d_GBps": in_b / h2d / 1e6, "d2h_ms": d2h, "d2h_GBps": out_b / d2h / 1e6,
+            "pcie_inclusive_points_per_s": n / ((h2d + ms_step + d2h) / 1000.0),
+            "note": "best of %d; pinned host buffers; not part of value" % reps}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -429,6 +461,7 @@ def main() -> int:
         "work": {k: work[k] for k in dpc.WORK_FIELDS},
         "roofline": roofline,
     }
+    rec["transfers"] = transfers(torch, inst, ms)
     if not args.no_fenwick:
         print("bench: Fenwick-tree dependent backend", file=sys.stderr, flush=True)
         rec["fenwick"] = fenwick(torch, dpc, inst, P, out)

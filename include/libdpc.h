@@ -232,7 +232,12 @@ typedef struct {
  * Returns DPC_OK if every instance succeeded, otherwise the first failing
  * instance's status (or a runtime error, after which outputs are
  * unspecified).  Reads back the coordinate bounds of each dimension's
- * instances once (synchronising the stream).
+ * instances once (synchronising the stream).  When the instances span
+ * several dimensions, each dimension runs on a stream and host thread that
+ * the library creates for the call (default priority, on the current
+ * device); those streams first wait for the work already queued on
+ * `stream`, and `stream` then waits for them, so the call is ordered on
+ * `stream` as a single-stream call would be.
  */
 DPC_API int dpc_batch_run(dpc_instance *instances, int32_t count, uint32_t flags, hipStream_t stream);
 

@@ -112,3 +112,18 @@ def test_backend_setting_and_autotuner_keep_outputs():
         same(host(dpc.run(P, x.d_cut, x.rho_min, x.delta_min)), ref, "after the backend autotuner")
     finally:
         dpc.set_dependent_backend(3, before)
+
+
+def test_degenerate_inputs():
+    # every point the same (all distances 0, all densities n), equally spaced
+    # collinear points (a distance tie at every step), and a cluster with one
+    # far point; sizes reach the k-d tree ranges
+    cases = [np.zeros((n, 2), np.int32) for n in (1500, 5000)]
+    cases.append(np.stack([np.arange(3000) * 7, np.zeros(3000)], 1).astype(np.int32))
+    blob = datagen.clustered_small(91, 4000, 3, span=1 << 12, k=1, sd_frac=0.05)
+    blob[17] = [1 << 28, 1 << 28, 1 << 28]
+    cases.append(blob)
+    for k, pts in enumerate(cases):
+        for d_cut, rho_min, delta_min in ((0.0, 1, 1.0), (10.0, 2, 30.0)):
+            got = host(dpc.run(dev(pts), d_cut, rho_min, delta_min, fenwick=True))
+            same(got, oracle.run(pts, d_cut, rho_min, delta_min), f"case {k} n={pts.shape[0]} d_cut={d_cut}")

@@ -166,8 +166,28 @@ def batched(torch, dpc, datagen, steps: int) -> dict:
             for a, b in zip(r, o):
                 if not torch.equal(a, b):
                     raise RuntimeError("batched and per-instance outputs differ")
+    # the same batch recorded once and replayed as a HIP graph (all on one
+    # stream: no host work, no library streams)
+    s = torch.cuda.Stream()
+    gouts = [tuple(torch.empty_like(t) for t in r) for r in B.results]
+    with dpc.BatchPlan(probs, outs=gouts, stream=s) as plan:
+        plan.capture(s)
+        plan.launch(s)
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.launch(s)
+        s.synchronize()
+        t_graph = (time.perf_counter() - t0) / steps
+        graph_ok = plan.status(s) == 0
+    for r, o in zip(B.results, gouts):
+        for a, b in zip(r, o):
+            if not torch.equal(a, b):
+                raise RuntimeError("graph replay and batched outputs differ")
     return {"workload": "batch512", "instances": len(insts), "points": total,
             "dims": sorted({x.d for x in insts}), "steps": steps,
+            "plan_graph_ms_per_batch": t_graph * 1000.0, "plan_graph_instances_per_s": len(insts) / t_graph,
+            "plan_status_ok": bool(graph_ok),
             "instances_per_s": len(insts) / t_batch, "ms_per_batch": t_batch * 1000.0,
             "points_per_s": total / t_batch,
             "loop_1stream_instances_per_s": len(insts) / timings[1],

@@ -288,6 +288,16 @@ typedef struct dpc_plan dpc_plan; /* opaque */
 DPC_API int dpc_plan_create(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,
                             double delta_min, uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2,
                             int32_t *label, hipStream_t stream, dpc_plan **out);
+/*
+ * dpc_plan_create_batch: the same for dpc_batch_run: records the batch
+ *   (instances and flags as for dpc_batch_run; every record's status is
+ *   set) and keeps it for replay.  Every instance must succeed, otherwise
+ *   the first failing status is returned and no plan is made.  The record
+ *   array itself is not kept.  A replay checks every instance against its
+ *   planned bounds.  All dimensions run on `stream` (no library streams).
+ */
+DPC_API int dpc_plan_create_batch(dpc_instance *instances, int32_t count, uint32_t flags, hipStream_t stream,
+                                  dpc_plan **out);
 DPC_API int dpc_plan_launch(dpc_plan *plan, hipStream_t stream);
 DPC_API int dpc_plan_capture(dpc_plan *plan, hipStream_t stream);
 DPC_API int dpc_plan_status(dpc_plan *plan, hipStream_t stream, int32_t *status);

@@ -8,6 +8,7 @@ include/libdpc.h; this package is its thin Python binding.  See
 from ._binding import (  # noqa: F401
     BACKENDS,
     Batch,
+    BatchPlan,
     DPCError,
     Instance,
     EXPORTED,

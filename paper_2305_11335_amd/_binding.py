@@ -28,7 +28,8 @@ EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_batch
             "dpc_server_submit", "dpc_server_poll", "dpc_server_wait", "dpc_server_get_stats",
             "dpc_server_destroy", "dpc_set_leaf_size", "dpc_leaf_size", "dpc_autotune", "dpc_plan_create",
             "dpc_plan_launch", "dpc_plan_capture", "dpc_plan_status", "dpc_plan_destroy",
-            "dpc_set_dependent_backend", "dpc_dependent_backend", "dpc_autotune_dependent")
+            "dpc_set_dependent_backend", "dpc_dependent_backend", "dpc_autotune_dependent",
+            "dpc_plan_create_batch")
 
 
 class Stats(ctypes.Structure):
@@ -128,6 +129,8 @@ def load():
     lib.dpc_server_destroy.restype = ctypes.c_int
     lib.dpc_plan_create.argtypes = [P, i64, i32, dbl, i32, dbl, u32, P, P, P, P, P, ctypes.POINTER(P)]
     lib.dpc_plan_create.restype = ctypes.c_int
+    lib.dpc_plan_create_batch.argtypes = [ctypes.POINTER(Instance), ctypes.c_int32, u32, P, ctypes.POINTER(P)]
+    lib.dpc_plan_create_batch.restype = ctypes.c_int
     lib.dpc_plan_launch.argtypes = [P, P]
     lib.dpc_plan_launch.restype = ctypes.c_int
     lib.dpc_plan_capture.argtypes = [P, P]
@@ -509,6 +512,26 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class BatchPlan(Plan):
+    """A dpc_plan of a whole batch: batch_run() recorded once on the
+    problems' point tensors and the output tensors, then replayed with
+    launch() (optionally as a HIP graph after capture()).  results holds the
+    outputs per problem."""
+
+    def __init__(self, problems, skip_noise: bool = False, outs=None, stream=None):
+        self._b = Batch(problems, skip_noise, outs)
+        self.results = self._b.results
+        self.out = self.results
+        self._h = ctypes.c_void_p()
+        st = load().dpc_plan_create_batch(self._b.recs, self._b.count, self._b.flags, _stream(stream),
+                                          ctypes.byref(self._h))
+        if st != OK:
+            raise DPCError(st, "dpc_plan_create_batch")
+
+    def statuses(self):
+        return self._b.statuses()
 
 
 def set_leaf_size(d: int, leaf_points: int) -> None:

@@ -277,7 +277,7 @@ namespace {
 // arithmetic.  Sets the range errors of its instances; *range_error tells
 // whether there was one.
 dpc_status run_dimension(int d, const std::vector<int> &ids, const std::vector<Job> &all, dpc_instance *instances,
-                         hipStream_t stream, size_t *peak, bool *range_error) {
+                         hipStream_t stream, size_t *peak, bool *range_error, Workspace *persist) {
     *peak = 0;
     *range_error = false;
     std::vector<Job> jobs;
@@ -285,7 +285,9 @@ dpc_status run_dimension(int d, const std::vector<int> &ids, const std::vector<J
         jobs.push_back(all[i]);
     std::vector<int> bad;
     {
-        Workspace ws(stream);
+        // (persist: a plan records the call and keeps every allocation)
+        Workspace local(stream);
+        Workspace &ws = persist ? *persist : local;
         const dpc_status st = job_bounds(jobs, d, ws, &bad);
         *peak = ws.bytes > *peak ? ws.bytes : *peak;
         if (st != DPC_OK && st != DPC_ERR_RANGE)
@@ -308,7 +310,8 @@ dpc_status run_dimension(int d, const std::vector<int> &ids, const std::vector<J
         // first, so the group does not end on one large instance's tail
         std::stable_sort(group.begin(), group.end(), [](const Job &x, const Job &y) { return x.n > y.n; });
         if (!group.empty()) {
-            Workspace ws(stream);
+            Workspace local(stream);
+            Workspace &ws = persist ? *persist : local;
             const dpc_status st = run_group(group, d, arith, nullptr, nullptr, ws);
             *peak = ws.bytes > *peak ? ws.bytes : *peak;
             if (st != DPC_OK)
@@ -321,7 +324,7 @@ dpc_status run_dimension(int d, const std::vector<int> &ids, const std::vector<J
 }  // namespace
 
 dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int count, hipStream_t stream,
-                         size_t *peak_bytes) {
+                         size_t *peak_bytes, Workspace *persist) {
     // checks, then groups by dimension
     std::vector<std::vector<int>> by_d(kMaxDim + 1);
     std::vector<Job> all(count);
@@ -342,10 +345,11 @@ dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int cou
     std::vector<dpc_status> st(dims.size(), DPC_OK);
     std::vector<size_t> peak(dims.size(), 0);
     std::vector<char> range(dims.size(), 0);
-    if (dims.size() <= 1) {
+    if (dims.size() <= 1 || persist) {
+        // (a plan records on this thread and stream only)
         for (size_t k = 0; k < dims.size(); ++k) {
             bool r = false;
-            st[k] = run_dimension(dims[k], by_d[dims[k]], all, instances, stream, &peak[k], &r);
+            st[k] = run_dimension(dims[k], by_d[dims[k]], all, instances, stream, &peak[k], &r, persist);
             range[k] = r;
         }
     } else {
@@ -375,7 +379,8 @@ dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int cou
                         return;
                     }
                     bool r = false;
-                    st[k] = run_dimension(dims[k], by_d[dims[k]], all, instances, streams[k], &peak[k], &r);
+                    st[k] = run_dimension(dims[k], by_d[dims[k]], all, instances, streams[k], &peak[k], &r,
+                                          nullptr);
                     range[k] = r;
                     if (hipEventRecord(done[k], streams[k]) != hipSuccess && st[k] == DPC_OK)
                         st[k] = DPC_ERR_HIP;
@@ -406,9 +411,8 @@ dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int cou
         if (range[k] && first_error == DPC_OK)
             first_error = DPC_ERR_RANGE;
         // concurrent dimensions hold their workspaces at the same time
-        total += dims.size() > 1 ? peak[k] : 0;
-        if (dims.size() == 1)
-            total = peak[k];
+        const bool concurrent = dims.size() > 1 && !persist;
+        total = concurrent ? total + peak[k] : (peak[k] > total ? peak[k] : total);
     }
     if (peak_bytes)
         *peak_bytes = total;
@@ -471,8 +475,19 @@ dpc_status time_choice(const int32_t *points, int64_t n, int32_t d, double d_cut
 
 }  // namespace dpc
 
-// A recorded dpc_run: its workspace stays allocated and its kernel launches
-// (with their argument values) are kept for replay.
+namespace dpc {
+namespace {
+// First launch of every replay: the status word starts clear, and the
+// recorded bound checks set it to the range error.
+__global__ void k_plan_clear(int32_t *status) {
+    if (threadIdx.x == 0)
+        status[0] = 0;
+}
+}  // namespace
+}  // namespace dpc
+
+// A recorded dpc_run (or dpc_batch_run): its workspace stays allocated and
+// its kernel launches (with their argument values) are kept for replay.
 struct dpc_plan {
     dpc::Workspace *ws = nullptr;
     dpc::LaunchRecord ops;
@@ -756,12 +771,14 @@ int dpc_plan_create(const int32_t *points, int64_t n, int32_t d, double d_cut, i
         delete pl;
         return DPC_ERR_OOM;
     }
+    pl->ws->cap = std::numeric_limits<int>::max();
     dpc_status st = DPC_OK;
     if (n > 0) {
         st = pl->ws->alloc(&pl->status, 1);
         if (st == DPC_OK) {
             t_record = &pl->ops;
             t_plan_status = pl->status;
+            launch(k_plan_clear, dim3(1), dim3(kWave), 0, stream, pl->status);
             std::vector<Job> jobs{J};
             st = job_bounds(jobs, d, *pl->ws, nullptr);
             if (st == DPC_OK)
@@ -772,6 +789,54 @@ int dpc_plan_create(const int32_t *points, int64_t n, int32_t d, double d_cut, i
         if (st == DPC_OK && hipStreamSynchronize(stream) != hipSuccess)
             st = DPC_ERR_HIP;
     }
+    if (st != DPC_OK) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(stream);
+        delete pl->ws;
+        delete pl;
+        return st;
+    }
+    *out = pl;
+    return DPC_OK;
+}
+
+int dpc_plan_create_batch(dpc_instance *instances, int32_t count, uint32_t flags, hipStream_t stream,
+                          dpc_plan **out) {
+    if (out == nullptr)
+        return DPC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (count < 0 || (count > 0 && instances == nullptr) || (flags & ~(uint32_t)DPC_SKIP_NOISE_DEPENDENTS))
+        return DPC_ERR_INVALID_ARG;
+    // every instance must be valid: the plan replays all of them
+    int first = DPC_OK;
+    for (int i = 0; i < count; ++i) {
+        instances[i].status = check_instance(instances[i], flags);
+        if (instances[i].status != DPC_OK && first == DPC_OK)
+            first = instances[i].status;
+    }
+    if (first != DPC_OK)
+        return first;
+    dpc_plan *pl = new (std::nothrow) dpc_plan;
+    if (pl == nullptr)
+        return DPC_ERR_OOM;
+    pl->ws = new (std::nothrow) Workspace(stream);
+    if (pl->ws == nullptr) {
+        delete pl;
+        return DPC_ERR_OOM;
+    }
+    pl->ws->cap = std::numeric_limits<int>::max();
+    dpc_status st = pl->ws->alloc(&pl->status, 1);
+    if (st == DPC_OK) {
+        t_record = &pl->ops;
+        t_plan_status = pl->status;
+        launch(k_plan_clear, dim3(1), dim3(kWave), 0, stream, pl->status);
+        std::vector<uint32_t> fl((size_t)count, flags);
+        st = run_instances(instances, fl.data(), count, stream, nullptr, pl->ws);
+        t_record = nullptr;
+        t_plan_status = nullptr;
+    }
+    if (st == DPC_OK && hipStreamSynchronize(stream) != hipSuccess)
+        st = DPC_ERR_HIP;
     if (st != DPC_OK) {
         (void)hipGetLastError();
         (void)hipStreamSynchronize(stream);

@@ -136,19 +136,22 @@ struct Index {
 hipMemPool_t workspace_pool();
 
 // Stream-ordered device workspace: every allocation is released together.
+// A call's workspace holds at most kCap allocations (the workspace bound
+// counts on it); a plan's, which keeps every call it records, is unlimited.
 struct Workspace {
     hipStream_t stream;
     static constexpr int kCap = 160;
-    void *ptrs[kCap];
+    std::vector<void *> ptrs;
     int count = 0;
+    int cap = kCap;
     size_t bytes = 0;  // allocated so far, each allocation rounded up to 256 bytes
     hipMemPool_t pool;
-    explicit Workspace(hipStream_t s) : stream(s), pool(workspace_pool()) {}
+    explicit Workspace(hipStream_t s) : stream(s), pool(workspace_pool()) { ptrs.reserve(kCap); }
     ~Workspace() { release(); }
     template <class T>
     dpc_status alloc(T **out, size_t elems) {
         *out = nullptr;
-        if (count >= kCap)
+        if (count >= cap)
             return DPC_ERR_OOM;
         void *p = nullptr;
         const size_t want = bytes_rounded(elems * sizeof(T));
@@ -157,7 +160,8 @@ struct Workspace {
             (void)hipGetLastError();
             return DPC_ERR_OOM;
         }
-        ptrs[count++] = p;
+        ptrs.push_back(p);
+        ++count;
         bytes += want;
         *out = static_cast<T *>(p);
         return DPC_OK;
@@ -165,6 +169,7 @@ struct Workspace {
     void release() {
         for (int i = 0; i < count; ++i)
             (void)hipFreeAsync(ptrs[i], stream);
+        ptrs.clear();
         count = 0;
     }
     static size_t bytes_rounded(size_t b) { return ((b == 0 ? 256 : b) + 255) & ~(size_t)255; }
@@ -292,7 +297,8 @@ dpc_status launch_cluster_sweep(int64_t n, const int32_t *rho, const int32_t *de
 // DPC_SKIP_NOISE_DEPENDENTS); sets each record's status and returns the first
 // failure.  peak_bytes (optional) receives the largest workspace held at once.
 dpc_status run_instances(dpc_instance *instances, const uint32_t *flags, int count, hipStream_t stream,
-                         size_t *peak_bytes);
+                         size_t *peak_bytes,
+                         Workspace *persist = nullptr);
 
 // The argument checks of dpc_run for one instance (host only).
 dpc_status check_instance(const dpc_instance &q, uint32_t flags);

@@ -65,13 +65,32 @@ struct Box {
     int32_t hi[kMaxDim];
 };
 
+// (A replay clears the status word first; a check only ever sets the range
+// error, so the checks of several dimensions add up.)
 __global__ void k_bounds_check(const int32_t *__restrict__ mm, Box planned, int d, int32_t *status) {
     if (threadIdx.x == 0) {
         bool ok = true;
         for (int k = 0; k < d; ++k)
             ok = ok && mm[k] >= planned.lo[k] && mm[kMaxDim + k] <= planned.hi[k];
-        status[0] = ok ? 0 : (int32_t)DPC_ERR_RANGE;
+        if (!ok)
+            status[0] = (int32_t)DPC_ERR_RANGE;
     }
+}
+
+// The same for every instance of a group: mm and planned are
+// [count][lo[kMaxDim], hi[kMaxDim]].
+__global__ void k_bounds_check_group(const int32_t *__restrict__ mm, const int32_t *__restrict__ planned, int count,
+                                     int d, int32_t *status) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count)
+        return;
+    const int32_t *m = mm + (int64_t)i * 2 * kMaxDim;
+    const int32_t *p = planned + (int64_t)i * 2 * kMaxDim;
+    bool ok = true;
+    for (int k = 0; k < d; ++k)
+        ok = ok && m[k] >= p[k] && m[kMaxDim + k] <= p[kMaxDim + k];
+    if (!ok)
+        status[0] = (int32_t)DPC_ERR_RANGE;
 }
 
 __global__ void k_bounds_init(int32_t *mm) {
@@ -356,6 +375,17 @@ dpc_status job_bounds(std::vector<Job> &jobs, int d, Workspace &ws, std::vector<
         }
         DPC_HIP(hipGetLastError());
         DPC_HIP(hipMemcpyAsync(host_mm.data(), mm, host_mm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (t_record && t_plan_status) {
+            // a plan's replays check every instance against the bounds read now
+            DPC_HIP(hipStreamSynchronize(s));
+            int32_t *planned;
+            DPC_TRY(ws.alloc(&planned, host_mm.size()));
+            DPC_HIP(hipMemcpyAsync(planned, host_mm.data(), host_mm.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   s));
+            launch(k_bounds_check_group, dim3(blocks_for(count, kThreads)), dim3(kThreads), 0, s,
+                   (const int32_t *)mm, (const int32_t *)planned, count, d, t_plan_status);
+            DPC_HIP(hipGetLastError());
+        }
     }
     DPC_HIP(hipStreamSynchronize(s));
     dpc_status st = DPC_OK;

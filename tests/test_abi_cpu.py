@@ -35,7 +35,8 @@ def test_header_declares_the_interface():
                                   "dpc_server_create", "dpc_server_submit", "dpc_server_poll", "dpc_server_wait",
                                   "dpc_server_get_stats", "dpc_server_destroy", "dpc_plan_create", "dpc_plan_launch",
                                   "dpc_plan_capture", "dpc_plan_status", "dpc_plan_destroy",
-                                  "dpc_set_dependent_backend", "dpc_dependent_backend", "dpc_autotune_dependent"])
+                                  "dpc_set_dependent_backend", "dpc_dependent_backend", "dpc_autotune_dependent",
+                                  "dpc_plan_create_batch"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -250,6 +251,15 @@ def test_plan_argument_errors():
     assert lib.dpc_plan_create(fake, 5, 2, float("nan"), 0, 1.0, 0, *outs, ctypes.byref(h)) == E
     assert lib.dpc_plan_create(fake, 5, 2, 1.0, -1, 1.0, 0, *outs, ctypes.byref(h)) == E
     assert lib.dpc_plan_create(*args, 0, fake, NULL, fake, fake, NULL, ctypes.byref(h)) == E
+    recs = (dpc.Instance * 2)()
+    assert lib.dpc_plan_create_batch(recs, 2, 0, None, None) == E  # no place for the plan
+    assert lib.dpc_plan_create_batch(recs, 2, 8, None, ctypes.byref(h)) == E  # only the skip-noise flag
+    assert lib.dpc_plan_create_batch(None, 2, 0, None, ctypes.byref(h)) == E
+    assert lib.dpc_plan_create_batch(recs, -1, 0, None, ctypes.byref(h)) == E
+    recs[0] = dpc.Instance(0x1000, 5, 9, 1.0, 0, 1.0, 0x1000, 0x1000, 0x1000, 0x1000, -1)  # d out of range
+    recs[1] = dpc.Instance(0x1000, 5, 2, 1.0, 0, 1.0, 0x1000, 0x1000, 0x1000, 0x1000, -1)
+    assert lib.dpc_plan_create_batch(recs, 2, 0, None, ctypes.byref(h)) == E  # no plan with a failing instance
+    assert recs[0].status == E and recs[1].status == 0 and h.value is None
     st = ctypes.c_int32()
     assert lib.dpc_plan_launch(None, None) == E
     assert lib.dpc_plan_capture(None, fake) == E

@@ -171,3 +171,59 @@ def test_plan_creation_errors_match_dpc_run():
     with pytest.raises(dpc.DPCError) as e:
         dpc.Plan(P, 1.0, 1, 1.0)
     assert e.value.status == _binding.ERR_RANGE
+
+
+def test_batch_plan_replays_match_batch_run():
+    insts = datagen.batch_instances(seed=21, count=24, n_hi=8000)
+    probs = [(x.points, x.d_cut, x.rho_min, x.delta_min) for x in insts]
+    P = [dev(p) for p, *_ in probs]
+
+    def batch_now():
+        outs, st = dpc.batch_run([(t, dc, rm, dm) for t, (_, dc, rm, dm) in zip(P, probs)], check=False)
+        assert st == [0] * len(probs)
+        return [host(o) for o in outs]
+
+    want = batch_now()
+    s = torch.cuda.Stream()
+    with dpc.BatchPlan([(t, dc, rm, dm) for t, (_, dc, rm, dm) in zip(P, probs)], stream=s) as plan:
+        assert plan.statuses() == [0] * len(probs)
+        for k in range(len(probs)):
+            same(host(plan.results[k]), want[k], f"created, instance {k}")
+        for rep in range(3):
+            news = [within(p, p, 300 + 17 * rep + i) for i, (p, *_) in enumerate(probs)]
+            for t, a in zip(P, news):
+                t.copy_(dev(a))
+            torch.cuda.synchronize()
+            if rep == 1:
+                plan.capture(s)
+            plan.launch(s)
+            assert plan.status(s) == 0
+            s.synchronize()
+            ref = batch_now()
+            for k in range(len(probs)):
+                same(host(plan.results[k]), ref[k], f"replay {rep}, instance {k}")
+            say("batch plan replay", rep, "ok")
+        # one instance's point leaves its planned bounds: the range status,
+        # then exact results again once it is back
+        moved = news[3].copy()
+        moved[0] = news[3].max(axis=0) + 5
+        P[3].copy_(dev(moved))
+        torch.cuda.synchronize()
+        plan.launch(s)
+        assert plan.status(s) == _binding.ERR_RANGE
+        P[3].copy_(dev(news[3]))
+        torch.cuda.synchronize()
+        plan.launch(s)
+        assert plan.status(s) == 0
+        s.synchronize()
+        ref = batch_now()
+        for k in range(len(probs)):
+            same(host(plan.results[k]), ref[k], f"after the range case, instance {k}")
+
+
+def test_batch_plan_refuses_a_failing_instance():
+    good = datagen.clustered_small(5, 3000, 2, span=1 << 16)
+    wide = np.array([[0, 0], [2**31 - 1, 2**31 - 1], [-2**31, -2**31]], np.int32)
+    with pytest.raises(dpc.DPCError) as e:
+        dpc.BatchPlan([(dev(good), 700.0, 3, 2800.0), (dev(wide), 1.0, 0, 1.0)])
+    assert e.value.status == _binding.ERR_RANGE

@@ -310,7 +310,10 @@ dpc_status run_dimension(int d, const std::vector<int> &ids, const std::vector<J
         // first, so the group does not end on one large instance's tail
         std::stable_sort(group.begin(), group.end(), [](const Job &x, const Job &y) { return x.n > y.n; });
         if (!group.empty()) {
-            Workspace local(stream);
+            uint64_t bound = 0;  // a group takes at most the sum of its instances' bounds
+            for (const Job &J : group)
+                bound += workspace_bound(J.n, d);
+            Workspace local(stream, bound);
             Workspace &ws = persist ? *persist : local;
             const dpc_status st = run_group(group, d, arith, nullptr, nullptr, ws);
             *peak = ws.bytes > *peak ? ws.bytes : *peak;
@@ -449,7 +452,7 @@ dpc_status time_choice(const int32_t *points, int64_t n, int32_t d, double d_cut
     dpc_status st = DPC_OK;
     for (int r = 0; r < 3 && st == DPC_OK; ++r) {
         std::vector<Job> jobs{J};
-        Workspace run_ws(stream);
+        Workspace run_ws(stream, workspace_bound(n, d));
         if (hipEventRecord(e0, stream) != hipSuccess)
             st = DPC_ERR_HIP;
         if (st == DPC_OK)
@@ -652,7 +655,7 @@ int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t r
         return DPC_OK;
     RunRecorder rec(flags, stream);
     DPC_TRY(rec.begin());
-    Workspace ws(stream);
+    Workspace ws(stream, workspace_bound(n, d));
     int64_t *counters = nullptr;
     if (flags & DPC_COUNT_WORK) {
         DPC_TRY(ws.alloc(&counters, kCounters));

@@ -138,39 +138,69 @@ hipMemPool_t workspace_pool();
 // Stream-ordered device workspace: every allocation is released together.
 // A call's workspace holds at most kCap allocations (the workspace bound
 // counts on it); a plan's, which keeps every call it records, is unlimited.
+// Given a reserve (a bound on what the call will take), the first
+// allocation takes that much from the pool at once and later ones are carved
+// from it: one pool allocation and one free per call instead of one per
+// array (each costs tens of microseconds of host time).  Anything beyond the
+// reserve is allocated on its own.
 struct Workspace {
     hipStream_t stream;
     static constexpr int kCap = 160;
-    std::vector<void *> ptrs;
-    int count = 0;
+    std::vector<void *> ptrs;  // pool allocations, released together
+    int count = 0;             // arrays handed out
     int cap = kCap;
-    size_t bytes = 0;  // allocated so far, each allocation rounded up to 256 bytes
+    size_t bytes = 0;  // handed out so far, each array rounded up to 256 bytes
+    size_t reserve = 0;
+    char *chunk = nullptr;  // the reserve, once allocated
+    size_t used = 0;        // bytes of the reserve handed out
     hipMemPool_t pool;
-    explicit Workspace(hipStream_t s) : stream(s), pool(workspace_pool()) { ptrs.reserve(kCap); }
+    explicit Workspace(hipStream_t s, size_t reserve_bytes = 0)
+        : stream(s), reserve(reserve_bytes), pool(workspace_pool()) {
+        ptrs.reserve(8);
+    }
     ~Workspace() { release(); }
+    void *pool_alloc(size_t b) {
+        void *p = nullptr;
+        const hipError_t e = pool ? hipMallocFromPoolAsync(&p, b, pool, stream) : hipMallocAsync(&p, b, stream);
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        ptrs.push_back(p);
+        return p;
+    }
     template <class T>
     dpc_status alloc(T **out, size_t elems) {
         *out = nullptr;
         if (count >= cap)
             return DPC_ERR_OOM;
-        void *p = nullptr;
         const size_t want = bytes_rounded(elems * sizeof(T));
-        const hipError_t e = pool ? hipMallocFromPoolAsync(&p, want, pool, stream) : hipMallocAsync(&p, want, stream);
-        if (e != hipSuccess || p == nullptr) {
-            (void)hipGetLastError();
-            return DPC_ERR_OOM;
+        void *p = nullptr;
+        if (reserve > 0 && chunk == nullptr) {
+            chunk = static_cast<char *>(pool_alloc(bytes_rounded(reserve)));
+            if (chunk == nullptr)
+                reserve = 0;  // fall back to one allocation per array
         }
-        ptrs.push_back(p);
+        if (chunk != nullptr && used + want <= bytes_rounded(reserve)) {
+            p = chunk + used;
+            used += want;
+        } else {
+            p = pool_alloc(want);
+            if (p == nullptr)
+                return DPC_ERR_OOM;
+        }
         ++count;
         bytes += want;
         *out = static_cast<T *>(p);
         return DPC_OK;
     }
     void release() {
-        for (int i = 0; i < count; ++i)
-            (void)hipFreeAsync(ptrs[i], stream);
+        for (void *p : ptrs)
+            (void)hipFreeAsync(p, stream);
         ptrs.clear();
         count = 0;
+        chunk = nullptr;
+        used = 0;
     }
     static size_t bytes_rounded(size_t b) { return ((b == 0 ? 256 : b) + 255) & ~(size_t)255; }
 };

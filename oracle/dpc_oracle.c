@@ -140,16 +140,12 @@ void oracle_density_at(const int32_t *P, int64_t n, int32_t d, int64_t T,
     }
 }
 
-/* Definition 1 for every point. */
+/* Definition 1 for every point: each point is queried on its own, so every
+ * pin of the whole-array density also pins the per-query form above. */
 void oracle_density(const int32_t *P, int64_t n, int32_t d, int64_t T, int32_t *rho)
 {
-    for (int64_t i = 0; i < n; i++) {
-        int64_t c = 0;
-        for (int64_t j = 0; j < n; j++)
-            if (sq_dist(P, d, i, j) <= (i128)T)
-                c++;
-        rho[i] = (int32_t)c;
-    }
+    for (int64_t i = 0; i < n; i++)
+        oracle_density_at(P, n, d, T, &i, 1, &rho[i]);
 }
 
 /* Definitions 2 and 3 for the queried points: the lexicographic minimum of

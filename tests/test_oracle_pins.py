@@ -144,6 +144,29 @@ def test_c_oracle_matches_python_oracle_random():
             assert x.tolist() == list(y), (case, n, d, span, d_cut)
 
 
+def test_per_query_forms_match_python_oracle():
+    """density_at and dependent_at (the references of the full-size GPU
+    checks) against the pure-Python oracle on tie-heavy inputs, with query
+    lists in random order and with repeats, radii 0 and infinity included
+    (Section 3, Definitions 1-3)."""
+    rng = random.Random(7)
+    for case in range(300):
+        n = rng.randint(1, 40)
+        d = rng.randint(1, 5)
+        span = rng.choice([2, 3, 5, 8, 20])
+        pts = datagen.random_small(1000 + case, n, d, span, offset=rng.randint(-20, 20))
+        d_cut = rng.choice([0.0, math.inf, 1.0, math.sqrt(2.0), rng.uniform(0, span)])
+        T = ref.square_threshold(d_cut, False)
+        want_rho = ref.density(pts.tolist(), T)
+        q = [rng.randrange(n) for _ in range(rng.randint(1, 2 * n))]
+        assert oracle.density_at(pts, T, np.array(q, np.int64)).tolist() == [want_rho[i] for i in q], case
+        # arbitrary densities (few distinct values) exercise the priority ties
+        rho = [rng.randint(1, 3) for _ in range(n)]
+        wd, wd2 = ref.dependent(pts.tolist(), rho)
+        gd, gd2 = oracle.dependent_at(pts, np.array(rho, np.int32), np.array(q, np.int64))
+        assert gd.tolist() == [wd[i] for i in q] and gd2.tolist() == [wd2[i] for i in q], case
+
+
 # ----------------------------------------------------------------------------
 # density against scipy's k-d tree (an independent library routine)
 

@@ -275,18 +275,60 @@ def test_deterministic_across_runs_and_streams():
         assert torch.equal(x, y.cpu()) and torch.equal(x, z)
 
 
-@pytest.mark.parametrize("name", ["varden2d_1m", "varden2d_10m", "uniform2d_10m", "mix3d_10m", "aniso8d_10m"])
-def test_full_size_sampled(name):
+def oracle_at(points, T, rho, q):
+    """The oracle's per-query density and dependent point (Section 3,
+    Definitions 1-3) for the queries q, split over the host threads (each
+    call is a plain O(n) scan per query; ctypes releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import cpu_baseline
+
+    workers = max(1, min(16, cpu_baseline.threads_available()))
+    chunks = [c for c in np.array_split(np.asarray(q, np.int64), workers) if c.size]
+    with ThreadPoolExecutor(workers) as ex:
+        dens = list(ex.map(lambda c: oracle.density_at(points, T, c), chunks))
+        deps = list(ex.map(lambda c: oracle.dependent_at(points, rho, c), chunks))
+    return (np.concatenate(dens), np.concatenate([a for a, _ in deps]), np.concatenate([b for _, b in deps]))
+
+
+def full_size_samples(rho, dep, d2, n, count=1000, seed=99):
+    """count random points plus the points whose searches are longest: the
+    densest point, every root, the points with the largest finite delta2
+    (density peaks) and the least dense points."""
+    rng = np.random.default_rng(seed)
+    q = rng.choice(n, size=count, replace=False)
+    finite = np.flatnonzero(dep >= 0)
+    peaks = finite[np.argsort(d2[finite])[-32:]]
+    sparse = np.argsort(rho, kind="stable")[:16]
+    extra = np.concatenate([[int(np.argmax(rho))], np.flatnonzero(dep < 0)[:8], peaks, sparse])
+    return np.unique(np.concatenate([q, extra])).astype(np.int64)
+
+
+FULL_SIZE = ["varden2d_1m", "varden2d_10m", "uniform2d_10m", "mix3d_10m",
+             pytest.param("aniso8d_10m", marks=pytest.mark.timeout(900))]
+
+
+@pytest.mark.parametrize("name", FULL_SIZE)
+def test_full_size_exact(name):
+    """The whole output arrays at full size, in the launch configuration
+    bench.py times: bit-equal to the independently written multithreaded CPU
+    k-d tree version (itself checked against the oracle on the CPU), at least
+    1000 sampled points bit-equal to the oracle's per-query definitions, and
+    the invariants that pin every output given rho."""
+    import cpu_baseline
+
     inst = datagen.make(name)
     say("full size", name, inst.n, inst.d, inst.d_cut)
     rho, dep, d2, lab = gpu_run(inst.points, inst.d_cut, inst.rho_min, inst.delta_min)
-    rng = np.random.default_rng(99)
-    q = rng.choice(inst.n, size=48, replace=False).astype(np.int64)
-    q = np.concatenate([q, [int(np.argmax(rho))], np.flatnonzero(dep < 0)[:4]]).astype(np.int64)
+    say("  cpu k-d tree version, threads", cpu_baseline.threads_available())
+    want = cpu_baseline.run(inst.points, inst.d_cut, inst.rho_min, inst.delta_min)
+    assert_same([rho, dep, d2, lab], want, f"{name} against the CPU version")
+    q = full_size_samples(rho, dep, d2, inst.n)
+    say("  oracle samples", q.size)
     T = oracle.square_threshold(inst.d_cut)
-    assert np.array_equal(rho[q], oracle.density_at(inst.points, T, q)), "sampled density"
-    wd, wd2 = oracle.dependent_at(inst.points, rho, q)
-    assert np.array_equal(dep[q], wd) and np.array_equal(d2[q], wd2), "sampled dependent"
+    w_rho, w_dep, w_d2 = oracle_at(inst.points, T, rho, q)
+    assert np.array_equal(rho[q], w_rho), "sampled density"
+    assert np.array_equal(dep[q], w_dep) and np.array_equal(d2[q], w_d2), "sampled dependent"
     check_invariants(inst.points, rho, dep, d2, lab, inst.rho_min, inst.delta_min)
 
 

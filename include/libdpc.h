@@ -75,7 +75,8 @@ typedef enum {
     DPC_ERR_RANGE = 2,       /* squared distances could exceed int64 */
     DPC_ERR_NOT_FOREST = 3,  /* dpc_cluster: a followed dependent edge does not rank higher */
     DPC_ERR_OOM = 4,         /* workspace allocation failed */
-    DPC_ERR_HIP = 5          /* a HIP runtime call failed */
+    DPC_ERR_HIP = 5,         /* a HIP runtime call failed */
+    DPC_ERR_SCRATCH = 6      /* dpc_run_noalloc: the instance needs more than its fixed scratch */
 } dpc_status;
 
 /* dpc_run flag: compute dependents only for points with rho >= rho_min, as
@@ -171,6 +172,35 @@ DPC_API int dpc_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const
 DPC_API int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,
             double delta_min, uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2,
             int32_t *label, hipStream_t stream);
+
+/*
+ * For callers that cannot allocate device memory: code that must not call
+ * hipMalloc or a stream-ordered allocator (tight serving loops, harnesses
+ * that forbid allocation).  Computes exactly what dpc_run computes, with
+ * every workspace array carved from a fixed scratch area instead of the
+ * library's memory pool: a static device array of DPC_NOALLOC_SCRATCH_BYTES
+ * that the library's code object holds on every device it runs on, until
+ * the process ends.  The call allocates no device memory and frees none.
+ *   Arguments and outputs as for dpc_run (device pointers; the caller
+ *   allocates the outputs).  flags: 0 or DPC_SKIP_NOISE_DEPENDENTS.  The
+ *   dependent points always come from the priority-search k-d tree, whatever
+ *   dpc_set_dependent_backend says.
+ *   Limit: an instance fits when dpc_workspace_bytes(n, d) is at most
+ *   DPC_NOALLOC_SCRATCH_BYTES (64 MiB: up to 706,560 points in 2-D,
+ *   524,288 in 3-D and 262,144 in 8-D); a larger one returns
+ *   DPC_ERR_SCRATCH before any GPU work.
+ *   The first call on a device looks up that device's copy of the scratch
+ *   (hipGetSymbolAddress, no allocation); DPC_ERR_HIP if that fails.
+ *   Synchronises the stream like dpc_run (the bounds read-back).
+ * Every call on one device shares that device's scratch, and the scratch
+ * keeps the last call's contents: calls that overlap in time on one device
+ * (on other streams or host threads) race on it and their outputs are
+ * unspecified.  Order such calls on one stream or with events.
+ */
+#define DPC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+DPC_API int dpc_run_noalloc(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,
+                            double delta_min, uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2,
+                            int32_t *label, hipStream_t stream);
 
 /*
  * Parameter sweeps (the decision-graph workflow of Section 3: the outputs for

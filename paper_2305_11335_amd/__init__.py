@@ -32,6 +32,9 @@ from ._binding import (  # noqa: F401
     leaf_size,
     load,
     run,
+    run_noalloc,
+    NOALLOC_SCRATCH_BYTES,
+    ERR_SCRATCH,
     set_dependent_backend,
     set_leaf_size,
     square_threshold,

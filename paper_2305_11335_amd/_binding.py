@@ -13,7 +13,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdpc.so")
 
-OK, ERR_INVALID_ARG, ERR_RANGE, ERR_NOT_FOREST, ERR_OOM, ERR_HIP = range(6)
+OK, ERR_INVALID_ARG, ERR_RANGE, ERR_NOT_FOREST, ERR_OOM, ERR_HIP, ERR_SCRATCH = range(7)
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DPC_NOALLOC_SCRATCH_BYTES
 SKIP_NOISE_DEPENDENTS = 1
 TIME_STAGES = 2
 COUNT_WORK = 4
@@ -29,7 +30,7 @@ EXPORTED = ("dpc_density", "dpc_dependent", "dpc_cluster", "dpc_run", "dpc_batch
             "dpc_server_destroy", "dpc_set_leaf_size", "dpc_leaf_size", "dpc_autotune", "dpc_plan_create",
             "dpc_plan_launch", "dpc_plan_capture", "dpc_plan_status", "dpc_plan_destroy",
             "dpc_set_dependent_backend", "dpc_dependent_backend", "dpc_autotune_dependent",
-            "dpc_plan_create_batch")
+            "dpc_plan_create_batch", "dpc_run_noalloc")
 
 
 class Stats(ctypes.Structure):
@@ -95,6 +96,8 @@ def load():
     lib.dpc_cluster.restype = ctypes.c_int
     lib.dpc_run.argtypes = [P, i64, i32, dbl, i32, dbl, u32, P, P, P, P, P]
     lib.dpc_run.restype = ctypes.c_int
+    lib.dpc_run_noalloc.argtypes = [P, i64, i32, dbl, i32, dbl, u32, P, P, P, P, P]
+    lib.dpc_run_noalloc.restype = ctypes.c_int
     lib.dpc_status_str.argtypes = [ctypes.c_int]
     lib.dpc_status_str.restype = ctypes.c_char_p
     lib.dpc_square_threshold.argtypes = [dbl, i32, P]
@@ -283,6 +286,28 @@ def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool =
                         _ptr(dep), _ptr(delta2), _ptr(label), _stream(stream))
     if st != OK:
         raise DPCError(st, "dpc_run")
+    return rho, dep, delta2, label
+
+
+def run_noalloc(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool = False, out=None,
+                stream=None):
+    """dpc_run_noalloc: the whole method with the library's fixed device
+    scratch instead of any allocation (outputs as for run; pass `out` to
+    allocate nothing at all)."""
+    torch = _torch()
+    n, d = _check_points(points)
+    dev = points.device
+    if out is None:
+        out = (None, None, None, None)
+    rho = _out(out[0], n, torch.int32, dev)
+    dep = _out(out[1], n, torch.int32, dev)
+    delta2 = _out(out[2], n, torch.int64, dev)
+    label = _out(out[3], n, torch.int32, dev)
+    flags = SKIP_NOISE_DEPENDENTS if skip_noise else 0
+    st = load().dpc_run_noalloc(_ptr(points), n, d, float(d_cut), int(rho_min), float(delta_min), flags,
+                                _ptr(rho), _ptr(dep), _ptr(delta2), _ptr(label), _stream(stream))
+    if st != OK:
+        raise DPCError(st, "dpc_run_noalloc")
     return rho, dep, delta2, label
 
 

@@ -10,6 +10,14 @@
 #include <mutex>
 #include <thread>
 
+// The scratch of dpc_run_noalloc: device memory beyond its inputs and
+// outputs that the library holds on every device it runs on (as a static
+// array of its code object) instead of allocating per call.  In host code
+// this name stands for a host-side shadow, not a device address: the device
+// address of each device's copy comes from hipGetSymbolAddress
+// (dpc::scratch_on_current_device) and only that address is ever used.
+static __device__ __align__(256) unsigned char scratch[DPC_NOALLOC_SCRATCH_BYTES];
+
 namespace dpc {
 
 // floor(r^2) or ceil(r^2) of the exact value of the double r, saturating at
@@ -91,6 +99,28 @@ hipMemPool_t workspace_pool() {
         pools[dev] = p;
     }
     return pools[dev];
+}
+
+// The device address of the scratch on the current device, looked up once
+// per device (with that device current) and kept; nullptr if the lookup fails.
+void *scratch_on_current_device() {
+    static std::mutex mu;
+    static void *addr[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        addr[dev] = p;
+    }
+    return addr[dev];
 }
 
 namespace {
@@ -511,6 +541,7 @@ const char *dpc_status_str(int status) {
     case DPC_ERR_NOT_FOREST: return "dependent edges do not form a forest of rising priority";
     case DPC_ERR_OOM: return "device workspace allocation failed";
     case DPC_ERR_HIP: return "HIP runtime error";
+    case DPC_ERR_SCRATCH: return "instance too large for the fixed scratch of dpc_run_noalloc";
     default: return "unknown status";
     }
 }
@@ -670,6 +701,30 @@ int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t r
         DPC_TRY(rec.read_counters(counters));
     rec.commit(ws.bytes);
     return DPC_OK;
+}
+
+int dpc_run_noalloc(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
+                    uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2, int32_t *label,
+                    hipStream_t stream) {
+    if (flags & ~(uint32_t)DPC_SKIP_NOISE_DEPENDENTS)
+        return DPC_ERR_INVALID_ARG;
+    Job J;
+    DPC_TRY(make_job(points, n, d, d_cut, rho_min, delta_min, flags, rho, dep, delta2, label, J));
+    if (n == 0)
+        return DPC_OK;
+    // the bound covers every array the call carves (checked on the host,
+    // before any GPU work)
+    if (workspace_bound(n, d) > DPC_NOALLOC_SCRATCH_BYTES)
+        return DPC_ERR_SCRATCH;
+    void *buf = scratch_on_current_device();
+    if (buf == nullptr)
+        return DPC_ERR_HIP;
+    Workspace ws(stream, buf, DPC_NOALLOC_SCRATCH_BYTES);
+    ws.cap = std::numeric_limits<int>::max();
+    std::vector<Job> jobs{J};
+    DPC_TRY(job_bounds(jobs, d, ws, nullptr));
+    const dpc_status st = run_group(jobs, d, job_arith(jobs[0], d), nullptr, nullptr, ws, false);
+    return st == DPC_ERR_OOM ? DPC_ERR_SCRATCH : st;
 }
 
 int dpc_batch_run(dpc_instance *instances, int32_t count, uint32_t flags, hipStream_t stream) {

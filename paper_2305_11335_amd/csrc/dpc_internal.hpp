@@ -143,6 +143,10 @@ hipMemPool_t workspace_pool();
 // from it: one pool allocation and one free per call instead of one per
 // array (each costs tens of microseconds of host time).  Anything beyond the
 // reserve is allocated on its own.
+//
+// A workspace over an external buffer (the allocation-free entry point's
+// scratch) carves every array from that buffer and never touches the pool:
+// a request beyond it fails with DPC_ERR_OOM.
 struct Workspace {
     hipStream_t stream;
     static constexpr int kCap = 160;
@@ -153,11 +157,15 @@ struct Workspace {
     size_t reserve = 0;
     char *chunk = nullptr;  // the reserve, once allocated
     size_t used = 0;        // bytes of the reserve handed out
-    hipMemPool_t pool;
+    hipMemPool_t pool = nullptr;
+    bool external = false;  // chunk is a caller's buffer of `reserve` bytes
     explicit Workspace(hipStream_t s, size_t reserve_bytes = 0)
         : stream(s), reserve(reserve_bytes), pool(workspace_pool()) {
         ptrs.reserve(8);
     }
+    // buffer: device memory of buffer_bytes (a multiple of 256), 256-byte aligned
+    Workspace(hipStream_t s, void *buffer, size_t buffer_bytes)
+        : stream(s), reserve(buffer_bytes), chunk(static_cast<char *>(buffer)), external(true) {}
     ~Workspace() { release(); }
     void *pool_alloc(size_t b) {
         void *p = nullptr;
@@ -176,6 +184,15 @@ struct Workspace {
             return DPC_ERR_OOM;
         const size_t want = bytes_rounded(elems * sizeof(T));
         void *p = nullptr;
+        if (external) {
+            if (want > reserve - used)
+                return DPC_ERR_OOM;
+            *out = reinterpret_cast<T *>(chunk + used);
+            used += want;
+            ++count;
+            bytes += want;
+            return DPC_OK;
+        }
         if (reserve > 0 && chunk == nullptr) {
             chunk = static_cast<char *>(pool_alloc(bytes_rounded(reserve)));
             if (chunk == nullptr)
@@ -199,8 +216,9 @@ struct Workspace {
             (void)hipFreeAsync(p, stream);
         ptrs.clear();
         count = 0;
-        chunk = nullptr;
         used = 0;
+        if (!external)
+            chunk = nullptr;
     }
     static size_t bytes_rounded(size_t b) { return ((b == 0 ? 256 : b) + 255) & ~(size_t)255; }
 };

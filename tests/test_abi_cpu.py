@@ -36,7 +36,7 @@ def test_header_declares_the_interface():
                                   "dpc_server_get_stats", "dpc_server_destroy", "dpc_plan_create", "dpc_plan_launch",
                                   "dpc_plan_capture", "dpc_plan_status", "dpc_plan_destroy",
                                   "dpc_set_dependent_backend", "dpc_dependent_backend", "dpc_autotune_dependent",
-                                  "dpc_plan_create_batch"])
+                                  "dpc_plan_create_batch", "dpc_run_noalloc"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -48,7 +48,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     assert dpc.status_str(0) == "ok"
-    for s in range(1, 6):
+    for s in range(1, 7):
         assert dpc.status_str(s) and dpc.status_str(s) != "unknown status"
     assert dpc.status_str(99) == "unknown status"
 
@@ -282,3 +282,29 @@ def test_dependent_backend_setting_is_host_only():
         dpc.set_dependent_backend(2, "grid")
     assert lib.dpc_autotune_dependent(None, 10, 2, 1.0, 0, 1.0, None, None, None) == E
     assert lib.dpc_autotune_dependent(None, 0, 2, 1.0, 0, 1.0, None, None, None) == E
+
+
+def test_noalloc_limits_are_host_only():
+    """dpc_run_noalloc refuses, before any device work, flags it does not
+    take, invalid arguments, and instances whose workspace bound exceeds its
+    fixed scratch (DPC_ERR_SCRATCH); empty input is a no-op."""
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case is decided on the host
+    E, S = 1, 6
+    cap = dpc.NOALLOC_SCRATCH_BYTES
+    lib = dpc.load()
+    args = lambda n, d, flags: (fake, n, d, 1.0, 0, 1.0, flags, fake, fake, fake, fake, NULL)  # noqa: E731
+    assert lib.dpc_run_noalloc(*args(10, 2, 2)) == E  # DPC_TIME_STAGES is not taken
+    assert lib.dpc_run_noalloc(*args(10, 2, 8)) == E  # nor DPC_FENWICK_DEPENDENTS
+    assert lib.dpc_run_noalloc(*args(10, 9, 0)) == E
+    assert lib.dpc_run_noalloc(NULL, 10, 2, 1.0, 0, 1.0, 0, fake, fake, fake, fake, NULL) == E
+    assert lib.dpc_run_noalloc(*args(0, 2, 0)) == 0
+    for d, lo in ((2, 700_000), (3, 520_000), (8, 260_000)):
+        # the largest instance that fits, by the same bound the call checks
+        a, b = 1, 1 << 24
+        while a < b:
+            m = (a + b + 1) // 2
+            a, b = (m, b) if lib.dpc_workspace_bytes(m, d) <= cap else (a, m - 1)
+        assert a >= lo, (d, a)
+        assert lib.dpc_run_noalloc(*args(a + 1, d, 0)) == S
+        assert lib.dpc_run_noalloc(*args(5_000_000, d, 1)) == S
+    assert dpc.status_str(S) != "unknown status"

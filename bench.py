@@ -44,9 +44,29 @@ sys.path.insert(0, ROOT)
 
 METRIC = "points/sec end-to-end exact DPC (10M 2D, 1 GPU); batched instances/s; p99 ms"
 # MI355X published peaks
-PEAK_FP64_VECTOR_TFLOPS = 78.6   # 256 CUs x 64 lanes x 2.4 GHz x 2 (an FMA counts twice)
+PEAK_LANE_TOPS = 39.3            # VALU lane-instructions/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 PEAK_HBM_GBPS = 8000.0
 ORACLE_SAMPLE = 32768            # points of the CPU-baseline sample
+CONFIG2 = ("mix3d_10m", "aniso8d_10m")  # the 10M-point 3-D and 8-D workloads
+
+
+def ops_per_pair(d: int, narrow: bool) -> float:
+    """VALU lane-instructions of one exact pair test (one query against one
+    point) on the cheapest exact path the kernels use, counted in this
+    build's gfx950 assembly: on narrow leaves, per packed word of two axes a
+    16-bit subtract and a dot product, then the sign bit and half an add3 to
+    count it (2 * ceil(d/2) + 1.5; 3.5 in 2-D); in exact doubles, d
+    subtractions, one multiply, d - 1 fused multiply-adds and about two
+    instructions to compare and keep the result (2d + 2)."""
+    return 2 * ((d + 1) // 2) + 1.5 if narrow else 2 * d + 2
+
+
+def alg_bytes_per_point(d: int) -> int:
+    """Compulsory HBM bytes per point of density + dependent + labels: read
+    the coordinates twice (4d each), write rho (4), read rho for the keys (4),
+    write dep and delta2 (12), read rho, dep, delta2 for the labels (16) and
+    write the label (4): 8d + 40."""
+    return 8 * d + 40
 
 
 def arith_of(points) -> str:
@@ -58,13 +78,12 @@ def arith_of(points) -> str:
     return "f64" if s < (1 << 53) else "int64"
 
 
-def profiled_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None if there is none for this workload or the kernel's
-    sources changed since the counters were taken."""
+def _profiled(path: str, kernel: str):
+    """The record of `kernel` in a committed rocprofv3 counter summary, or
+    None if there is none or the kernel's sources changed since the counters
+    were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"traversal_{workload}_hbm_bytes.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -76,7 +95,51 @@ def profiled_traffic(workload: str, kernel: str):
     for src in k["sources"]:
         with open(os.path.join(ROOT, "paper_2305_11335_amd", "csrc", src), "rb") as f:
             h.update(f.read())
-    return k["bytes"] if h.hexdigest() == k["source_sha256"] else None
+    return k if h.hexdigest() == k["source_sha256"] else None
+
+
+def profiled_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE, scaled by
+    a plain copy's readings) from the committed summary, or None."""
+    k = _profiled(os.path.join(ROOT, "profiles", f"traversal_{workload}_hbm_bytes.json"), kernel)
+    return None if k is None else k["bytes"]
+
+
+def profiled_valu(workload: str, kernel: str):
+    """VALU wave-instructions per launch of `kernel` (SQ_INSTS_VALU) from the
+    committed summary, or None."""
+    k = _profiled(os.path.join(ROOT, "profiles", f"traversal_{workload}_valu.json"), kernel)
+    return None if k is None else k["valu_wave_insts"]
+
+
+def roofline(inst, stage_ms: dict, work: dict, ms_step: float) -> dict:
+    """The dominant traversal kernel against the integer-ALU roofline, plus
+    the whole step against the HBM roofline (SURVEY's compulsory bytes).
+
+    achieved: the kernel's pair tests (counted by the instrumented kernels)
+    times the VALU lane-instructions of one exact pair test on its cheapest
+    path, over its average time (HIP events on the launch stream during the
+    timed steps).  valu_issue_frac: the VALU instructions the kernel really
+    issues (a committed SQ_INSTS_VALU profile) over the same time and peak,
+    when the profile matches the sources."""
+    dom = max(("density", "dependent"), key=lambda k: stage_ms[k])
+    pairs = work["density_pairs"] if dom == "density" else work["dependent_pairs"]
+    d = inst.d
+    narrow = dom == "density" and arith_of(inst.points) == "f64"
+    ops = ops_per_pair(d, narrow)
+    kernel_s = stage_ms[dom] / 1000.0
+    achieved = pairs * ops / kernel_s / 1e12
+    valu = profiled_valu(inst.name, f"k_{dom}")
+    alg = alg_bytes_per_point(d) * inst.n
+    return {"bound": "alu", "kernel": f"k_{dom}", "achieved": achieved, "peak": PEAK_LANE_TOPS,
+            "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_LANE_TOPS,
+            "traffic": profiled_traffic(inst.name, f"k_{dom}"),
+            "kernel_ms": stage_ms[dom], "pair_tests_per_launch": pairs, "lane_ops_per_pair_test": ops,
+            "pair_test_path": "packed 16-bit narrow leaf" if narrow else "exact double",
+            "valu_issue_frac": None if valu is None else valu * 64 / kernel_s / (PEAK_LANE_TOPS * 1e12),
+            "hbm_step": {"alg_bytes": alg, "achieved_GBps": alg / (ms_step / 1000.0) / 1e9,
+                         "peak_GBps": PEAK_HBM_GBPS, "frac": alg / (ms_step / 1000.0) / 1e9 / PEAK_HBM_GBPS,
+                         "target_frac": 0.40}}
 
 
 def cpu_baseline(inst) -> dict:
@@ -113,6 +176,37 @@ def cpu_parallel(inst, gpu_out) -> dict:
     return {"value": inst.n / dt, "unit": "points/s", "cores": threads, "kind": "cpu_kdtree_multithreaded",
             "sample": f"whole {inst.name} ({inst.n} points), one run, {dt:.2f} s",
             "outputs_identical_to_gpu": bool(same)}
+
+
+def single_workload(torch, dpc, datagen, name: str, steps: int, warmup: int) -> dict:
+    """One dpc_run per step on another single workload (the 10M-point 3-D
+    and 8-D sets): time per step, per-step GPU times, work counters and the
+    roofline of its dominant kernel, like the headline."""
+    inst = datagen.make(name)
+    dev = torch.device("cuda:0")
+    P = torch.from_numpy(inst.points).to(dev)
+    n = inst.n
+    out = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
+           torch.empty(n, dtype=torch.int64, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, out=out, stream=stream)
+    torch.cuda.synchronize()
+    stage_ms = {k: 0.0 for k in dpc.STAGES}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, out=out, stream=stream, time_stages=True)
+        for k, v in dpc.last_stats()["stage_ms"].items():
+            stage_ms[k] += v
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    stage_ms = {k: v / steps for k, v in stage_ms.items()}
+    dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, out=out, stream=stream, count_work=True)
+    work = dpc.last_stats()
+    torch.cuda.synchronize()
+    return {"workload": name, "n": n, "d": inst.d, "d_cut": inst.d_cut, "steps": steps, "ms_per_step": ms,
+            "points_per_s": n / (ms / 1000.0), "stage_ms": stage_ms,
+            "work": {k: work[k] for k in dpc.WORK_FIELDS}, "roofline": roofline(inst, stage_ms, work, ms)}
 
 
 def batched(torch, dpc, datagen, steps: int) -> dict:
@@ -397,6 +491,8 @@ def main() -> int:
     ap.add_argument("--workload", default="varden2d_10m")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip both CPU baselines")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
+    ap.add_argument("--no-config2", action="store_true", help="skip the 10M-point 3-D and 8-D workloads")
+    ap.add_argument("--config2-steps", type=int, default=5)
     ap.add_argument("--no-fenwick", action="store_true", help="skip the Fenwick-backend measurement")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-workload measurement")
@@ -452,15 +548,7 @@ def main() -> int:
         torch.cuda.synchronize()
 
     # dominant kernel: the longer of the two traversals (each stage is one kernel)
-    dom = max(("density", "dependent"), key=lambda k: stage_ms[k])
-    pairs = work["density_pairs"] if dom == "density" else work["dependent_pairs"]
-    flops_per_pair = 3 * d - 1  # d subtractions, d squares, d - 1 additions of one exact squared distance
-    kernel_s = stage_ms[dom] / 1000.0
-    achieved = pairs * flops_per_pair / kernel_s / 1e12
-    roofline = {"bound": "alu", "kernel": f"k_{dom}", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
-                "traffic": profiled_traffic(inst.name, f"k_{dom}"),
-                "kernel_ms": stage_ms[dom], "pair_tests_per_launch": pairs, "flops_per_pair_test": flops_per_pair}
+    roof = roofline(inst, stage_ms, work, ms)
 
     rec = {
         "metric": METRIC,
@@ -473,15 +561,20 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": arith_of(inst.points),
+        "dtype": "exact integer (i16 dot products, i24 box tests, f64 holding integers)",
         "data": "synthetic (seeded generator, see datagen)",
         "config": {"workload": inst.name, "n": n, "d": d, "d_cut": inst.d_cut, "rho_min": inst.rho_min,
                    "delta_min": inst.delta_min, "seed": inst.seed},
         "stage_ms": stage_ms,
         "work": {k: work[k] for k in dpc.WORK_FIELDS},
-        "roofline": roofline,
+        "roofline": roof,
     }
     rec["transfers"] = transfers(torch, inst, ms)
+    if not args.no_config2:
+        rec["config2"] = {}
+        for name in CONFIG2:
+            print(f"bench: {name}", file=sys.stderr, flush=True)
+            rec["config2"][name] = single_workload(torch, dpc, datagen, name, args.config2_steps, 1)
     if not args.no_fenwick:
         print("bench: Fenwick-tree dependent backend", file=sys.stderr, flush=True)
         rec["fenwick"] = fenwick(torch, dpc, inst, P, out)

@@ -338,9 +338,10 @@ DPC_API int dpc_plan_destroy(dpc_plan *plan);
  * requests).  A server owns `slots` host threads, each with a HIP stream of
  * its own on the device current at creation.  Requests wait in one queue in
  * arrival order; whenever a slot is free it takes the longest prefix of the
- * queue (at most max_batch requests) whose workspace bounds
- * (dpc_workspace_bytes), added to those of the requests already running,
- * stay within hbm_budget_bytes, and runs it as one batch.  A request that
+ * queue (at most max_batch requests) whose footprints, added to those of the
+ * requests already running, stay within hbm_budget_bytes, and runs it as one
+ * batch.  A request's footprint is its workspace bound (dpc_workspace_bytes)
+ * plus its own device arrays: n * (4d + 20) bytes of points and outputs.  A request that
  * arrives while batches run thus joins the next batch a slot forms, and
  * several batches overlap on the device.  Every request's outputs are
  * bit-identical to those of dpc_run with the same arguments, whatever it is
@@ -349,7 +350,7 @@ DPC_API int dpc_plan_destroy(dpc_plan *plan);
 typedef struct dpc_server dpc_server; /* opaque */
 
 typedef struct {
-    uint64_t hbm_budget_bytes; /* > 0: bound on the summed workspace bounds of the requests in flight */
+    uint64_t hbm_budget_bytes; /* > 0: bound on the summed footprints of the requests in flight */
     int32_t slots;             /* 1 .. 16: batches in flight at once */
     int32_t max_batch;         /* >= 1: requests per batch */
 } dpc_server_config;
@@ -360,7 +361,7 @@ typedef struct {
     int64_t submit_ns;   /* CLOCK_MONOTONIC times of submission, admission to a batch and completion */
     int64_t admit_ns;
     int64_t done_ns;
-    uint64_t footprint;  /* workspace bound charged against the budget while it ran */
+    uint64_t footprint;  /* bytes charged against the budget while it ran: workspace bound + n * (4d + 20) */
     int32_t batch_size;  /* requests in its batch */
     int32_t slot;        /* the slot that ran it */
 } dpc_request_info;
@@ -372,10 +373,10 @@ typedef struct {
     int64_t batches;              /* batches started */
     int64_t max_batch_seen;       /* largest batch */
     int32_t max_slots_busy;       /* most batches in flight at once */
-    uint64_t max_admitted_bytes;  /* largest summed bound of the requests in flight */
+    uint64_t max_admitted_bytes;  /* largest summed footprint of the requests in flight */
     uint64_t max_workspace_bytes; /* largest workspace a batch held */
-    int64_t over_footprint;       /* batches whose workspace exceeded their summed bound (a library bug if > 0) */
-    uint64_t in_flight_bytes;     /* now: summed bound of the requests in flight */
+    int64_t over_footprint;       /* batches whose workspace exceeded their summed footprint (a library bug if > 0) */
+    uint64_t in_flight_bytes;     /* now: summed footprint of the requests in flight */
     int64_t queued;               /* now: requests waiting */
 } dpc_server_stats;
 
@@ -387,7 +388,7 @@ DPC_API int dpc_server_create(const dpc_server_config *config, dpc_server **out)
  * Queues one request: a record as for dpc_batch_run (device pointers; status
  * is ignored) and flags 0 or DPC_SKIP_NOISE_DEPENDENTS.  The arrays must stay
  * valid and untouched until the request is done.  Argument errors are
- * returned at once (no ticket); DPC_ERR_OOM if the request's bound alone
+ * returned at once (no ticket); DPC_ERR_OOM if the request's footprint alone
  * exceeds the budget.  Otherwise *ticket identifies the request.
  */
 DPC_API int dpc_server_submit(dpc_server *server, const dpc_instance *request, uint32_t flags, uint64_t *ticket);

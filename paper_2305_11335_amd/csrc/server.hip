@@ -3,9 +3,10 @@
 // batching).  Each slot is a host thread with a HIP stream of its own, so
 // several batches are in flight on the device at once; a request that
 // arrives while they run joins the next batch that any slot forms.
-// Admission is first come, first served, bounded by the summed workspace
-// bound of the admitted requests (workspace_bound), which the batch
-// workspaces never exceed.  A batch is one run_instances call (the batched
+// Admission is first come, first served, bounded by the summed footprint of
+// the admitted requests: each one's workspace bound (workspace_bound, which
+// the batch workspaces never exceed) plus its own input and output arrays
+// (4d + 20 bytes per point), all of which are resident while it runs.  A batch is one run_instances call (the batched
 // path of dpc_batch_run), so every request's outputs are those of dpc_run
 // with the same arguments, whatever it was batched with.
 #include "dpc_internal.hpp"
@@ -187,7 +188,9 @@ int dpc_server_submit(dpc_server *s, const dpc_instance *req, uint32_t flags, ui
     r.inst.status = -1;
     r.flags = flags;
     r.info = dpc_request_info{};
-    r.info.footprint = workspace_bound(req->n, req->d);
+    // workspace, plus the caller's points (4d bytes per point) and the four
+    // outputs (rho, dep, label 4 bytes each, delta2 8)
+    r.info.footprint = workspace_bound(req->n, req->d) + (uint64_t)req->n * (4ull * (uint64_t)req->d + 20ull);
     r.info.submit_ns = now_ns();
     std::lock_guard<std::mutex> lk(s->mu);
     if (r.info.footprint > s->budget) {

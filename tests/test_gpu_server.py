@@ -99,13 +99,15 @@ def test_served_equals_alone_under_concurrent_arrivals():
 def test_batching_and_budget():
     reqs = pool(count=16, n_hi=60_000, seed=22)
     pts = [dev(x.points) for x in reqs]
-    fps = [dpc.workspace_bytes(x.n, x.d) for x in reqs]
+    # footprint: workspace bound plus the request's points and outputs
+    fps = [dpc.workspace_bytes(x.n, x.d) + x.n * (4 * x.d + 20) for x in reqs]
     # one slot and a queue filled at once: later requests are batched together
     with dpc.Server(hbm_budget_bytes=64 << 30, slots=1, max_batch=64) as srv:
         tk = [srv.submit(p, x.d_cut, x.rho_min, x.delta_min) for p, x in zip(pts, reqs)]
         infos = [srv.wait(t) for t, _ in tk]
         st = srv.stats()
     assert all(i["status"] == 0 for i in infos)
+    assert [i["footprint"] for i in infos] == fps
     assert st["batches"] < len(reqs) and st["max_batch_seen"] > 1
     for (t, res), x, p in zip(tk, reqs, pts):
         same(res, dpc.run(p, x.d_cut, x.rho_min, x.delta_min), "batched request")

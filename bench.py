@@ -19,10 +19,11 @@ and, for comparison, as a loop of per-instance dpc_run calls on one stream
 and on four streams (one host thread each); outputs of the three are
 compared bit for bit.
 
-A third, "served", replays a Poisson arrival stream (200 requests/s, n
-log-uniform in [1e3, 1e6], d = 3, uniform or clustered; requests drawn from a
-resident pool of 64 instances) through a dpc_server (HBM budget 200 GB) and
-reports p50/p99 latency (completion minus scheduled arrival) and throughput,
+A third, "served", replays a Poisson arrival stream (200 requests/s for 60 s
+after a 5 s warm-up, n log-uniform in [1e3, 1e6], d = 3, uniform or
+clustered; requests drawn from a resident pool of 256 instances) through a
+dpc_server (HBM budget 200 GB) and reports p50/p99 latency (completion minus
+scheduled arrival) and throughput,
 beside the same trace run as plain per-request dpc_run calls in arrival
 order; each pool instance's served outputs are compared with its dpc_run
 outputs.
@@ -209,16 +210,24 @@ def single_workload(torch, dpc, datagen, name: str, steps: int, warmup: int) -> 
             "work": {k: work[k] for k in dpc.WORK_FIELDS}, "roofline": roofline(inst, stage_ms, work, ms)}
 
 
-def batched(torch, dpc, datagen, steps: int) -> dict:
+def batched(torch, dpc, datagen, steps: int, trace_only: bool = False) -> dict:
     """Instances/s of the batched workload: one dpc_batch_run per step against
     per-instance dpc_run loops (one stream; four streams driven by one host
     thread each).  Inputs and outputs are resident; the three forms must give
-    identical outputs."""
+    identical outputs.  Before timing, the leaf size of each dimension is
+    autotuned on that dimension's largest instance.  trace_only: only the
+    timed dpc_batch_run calls (for a kernel trace of them)."""
     insts = datagen.batch_instances()
     dev = torch.device("cuda:0")
     pts = [torch.from_numpy(x.points).to(dev) for x in insts]
     probs = [(p, x.d_cut, x.rho_min, x.delta_min) for p, x in zip(pts, insts)]
     total = sum(x.n for x in insts)
+    tuned = {}
+    for d in sorted({x.d for x in insts}):
+        k = max((i for i, x in enumerate(insts) if x.d == d), key=lambda i: insts[i].n)
+        r = dpc.autotune(*probs[k])
+        tuned[str(d)] = {"instance_n": insts[k].n, "ms_leaf16": r["ms"][16], "ms_leaf32": r["ms"][32],
+                         "leaf_points": r["chosen"]}
     B = dpc.Batch(probs)
     B.run()  # warm-up (pool growth, code loading)
     torch.cuda.synchronize()
@@ -227,6 +236,9 @@ def batched(torch, dpc, datagen, steps: int) -> dict:
         B.run()
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / steps
+    if trace_only:
+        return {"workload": "batch512", "instances": len(insts), "points": total, "steps": steps,
+                "ms_per_batch": t_batch * 1000.0, "instances_per_s": len(insts) / t_batch, "autotuned": tuned}
 
     outs = [tuple(torch.empty_like(t) for t in r) for r in B.results]
 
@@ -279,7 +291,7 @@ def batched(torch, dpc, datagen, steps: int) -> dict:
             if not torch.equal(a, b):
                 raise RuntimeError("graph replay and batched outputs differ")
     return {"workload": "batch512", "instances": len(insts), "points": total,
-            "dims": sorted({x.d for x in insts}), "steps": steps,
+            "dims": sorted({x.d for x in insts}), "steps": steps, "autotuned": tuned,
             "plan_graph_ms_per_batch": t_graph * 1000.0, "plan_graph_instances_per_s": len(insts) / t_graph,
             "plan_status_ok": bool(graph_ok),
             "instances_per_s": len(insts) / t_batch, "ms_per_batch": t_batch * 1000.0,
@@ -496,8 +508,11 @@ def main() -> int:
     ap.add_argument("--no-fenwick", action="store_true", help="skip the Fenwick-backend measurement")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-workload measurement")
-    ap.add_argument("--serve-seconds", type=float, default=30.0)
-    ap.add_argument("--serve-warmup", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--serve-pool", type=int, default=256, help="distinct request instances")
+    ap.add_argument("--batch-trace", action="store_true",
+                    help="run only the batched workload's timed calls (for a kernel trace of them)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -510,6 +525,9 @@ def main() -> int:
     import datagen
     import paper_2305_11335_amd as dpc
 
+    if args.batch_trace:
+        print(json.dumps({"batched": batched(torch, dpc, datagen, args.batch_steps, trace_only=True)}), flush=True)
+        return 0
     inst = datagen.make(args.workload)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -585,7 +603,7 @@ def main() -> int:
     if not args.no_serve:
         print(f"bench: served workload ({args.serve_warmup + args.serve_seconds:.0f} s, twice)", file=sys.stderr,
               flush=True)
-        pool = datagen.served_instances()
+        pool = datagen.served_instances(count=args.serve_pool)
         pts = [torch.from_numpy(x.points).to(dev) for x in pool]
         rec["served"] = served(torch, dpc, pool, pts, args.serve_seconds, args.serve_warmup)
         # the same pool offered faster than per-request calls can serve it

@@ -8,10 +8,12 @@
 // the global minimum, as uint32, plus the id).  A node's median along its
 // split axis is found exactly by most-significant-digit radix select: each
 // pass histograms one digit of the points that still match the digits found
-// so far (11-bit digits while a level has few nodes, 8-bit below).  The node
-// is then partitioned stably: "less than the median" and "equal to the
-// median" flags are scanned, and the first equal points in array order fill
-// the left half.  The same pass reduces the children's boxes.
+// so far (11-bit digits while a level has few nodes, 8-bit below), and the
+// workgroup whose tiles complete a node's histogram picks the node's digit.
+// The node is then partitioned stably: "less than the median" and "equal to
+// the median" flags are counted per tile and scanned, and the first equal
+// points in array order fill the left half.  The same pass reduces the
+// children's boxes.
 //
 // Bottom levels: one workgroup owns a subtree of at most 2048 (d <= 3) or
 // 1024 points and keeps it in LDS.  On each level every wavefront takes whole
@@ -251,48 +253,79 @@ __host__ __device__ inline void digit_bits(int bits, int pass, int width, int &l
 
 // State of a node's radix select after some passes: the digits of the
 // median found so far (prefix), how many of the node's points lie below the
-// prefix range (less), and the median's rank among the points matching the
-// prefix (rank).
+// prefix range (less), the median's rank among the points matching the
+// prefix (rank) and how many points match it (match); and the count of the
+// node's tiles whose histogram additions of the current pass are issued
+// (arrive, cleared by the pick).
 struct SelectState {
-    uint32_t prefix, less, rank;
+    uint32_t prefix, less, rank, match;
+    uint32_t arrive;
 };
 
-// Chooses the digit of one pass from the node's histogram of that pass (all
-// threads of the block take part).
+// Bound on the polls of a wait for other workgroups' atomics (each poll
+// sleeps briefly): far beyond any real wait, it only keeps a wait from
+// running forever.
+constexpr uint32_t kMaxPolls = 1u << 16;
+
+__device__ inline uint32_t load_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Chooses the digit of one pass from the node's finished histogram (all
+// threads of the block take part).  Other workgroups completed the
+// histogram with relaxed device-scope atomics, which this reads with
+// relaxed device-scope loads (they reach the point where those atomics are
+// performed, without flushing any cache): the counts are read again until
+// they add up to the node's matching points, so every addition is in.
 template <int BITS>
 __device__ inline void pick_digit(const uint32_t *__restrict__ hp, int width, SelectState &st, uint32_t *s_w,
                                   uint32_t *s_pick) {
     using Dg = Digit<BITS>;
     uint32_t c[Dg::kPerThread];
-    uint32_t mine = 0;
+    uint32_t mine = 0, cum = 0;
+    for (uint32_t polls = 0;; ++polls) {
+        mine = 0;
 #pragma unroll
-    for (int b = 0; b < Dg::kPerThread; ++b) {
-        c[b] = hp[threadIdx.x * Dg::kPerThread + b];
-        mine += c[b];
+        for (int b = 0; b < Dg::kPerThread; ++b) {
+            c[b] = load_agent(hp + threadIdx.x * Dg::kPerThread + b);
+            mine += c[b];
+        }
+        cum = block_incl_scan(mine, s_w);
+        if (threadIdx.x == kThreads - 1)
+            s_pick[0] = cum;
+        __syncthreads();
+        const uint32_t total = s_pick[0];
+        __syncthreads();
+        if (total == st.match || polls >= kMaxPolls)
+            break;
+        __builtin_amdgcn_s_sleep(2);
     }
-    uint32_t cum = block_incl_scan(mine, s_w) - mine;
+    cum -= mine;
 #pragma unroll
     for (int b = 0; b < Dg::kPerThread; ++b) {
         if (cum <= st.rank && st.rank < cum + c[b]) {
             s_pick[0] = threadIdx.x * Dg::kPerThread + b;
             s_pick[1] = cum;
+            s_pick[2] = c[b];
         }
         cum += c[b];
     }
     __syncthreads();
-    const uint32_t dg = s_pick[0], below = s_pick[1];
+    const uint32_t dg = s_pick[0], below = s_pick[1], count = s_pick[2];
     __syncthreads();
     st.prefix = (st.prefix << width) | dg;
     st.less += below;
     st.rank -= below;
+    st.match = count;
 }
 
 // One pass of the radix select of every node of level j: each workgroup
 // histograms the digit of the points of `tiles` consecutive tiles (all in one
 // node) that still match the node's prefix, then adds its histogram to the
-// node's (k_sel_pick then chooses the digit).  Several tiles per workgroup
-// keep the number of global additions to one bin low on the first levels,
-// where every workgroup works on one of very few nodes.
+// node's; the workgroup whose tiles complete the node's histogram chooses the
+// digit and stores the node's state for the next pass.  Several tiles per
+// workgroup keep the number of global additions to one bin low on the first
+// levels, where every workgroup works on one of very few nodes.
 template <int D, int BITS>
 __global__ __launch_bounds__(kThreads) void k_sel_hist(const Inst *__restrict__ inst,
                                                        const uint32_t *__restrict__ tile_inst,
@@ -300,6 +333,9 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const Inst *__restrict__ 
                                                        int j, int pass) {
     using Dg = Digit<BITS>;
     __shared__ uint32_t s_h[Dg::kBins];
+    __shared__ uint32_t s_w[kWaves];
+    __shared__ uint32_t s_pick[3];
+    __shared__ uint32_t s_last;
     // this workgroup's tiles: from the table (a group), or `per` at a time
     int64_t tile;
     int tiles;
@@ -319,8 +355,14 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const Inst *__restrict__ 
     const NodeSelect ns = node_select<D, BITS>(nbox);
     if (pass >= ns.passes || tt.g.half == tt.g.count)
         return;  // this node's median is already known (or it has no right half)
-    const SelectState *state = static_cast<const SelectState *>(A.state) + I.S;
-    const SelectState st = pass == 0 ? SelectState{0u, 0u, (uint32_t)tt.g.half} : state[tt.t];
+    SelectState *state = static_cast<SelectState *>(A.state) + I.S;
+    SelectState st = {0u, 0u, (uint32_t)tt.g.half, (uint32_t)tt.g.count, 0u};
+    if (pass > 0) {
+        st.prefix = load_agent(&state[tt.t].prefix);
+        st.less = load_agent(&state[tt.t].less);
+        st.rank = load_agent(&state[tt.t].rank);
+        st.match = load_agent(&state[tt.t].match);
+    }
     int lo, hi;
     digit_bits(ns.bits, pass, BITS, lo, hi);
     const uint32_t dmask = (1u << (hi - lo)) - 1u;
@@ -329,12 +371,22 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const Inst *__restrict__ 
     __syncthreads();
     const uint32_t *x = A.X + (int64_t)ns.axis * A.positions + I.P;
     const int w = threadIdx.x / kWave;
+    uint32_t done_tiles = 0;
+    // the next tile's values are loaded before this tile's are counted, so
+    // two tiles' loads are in flight at once
+    uint32_t xn[kItems];
+    load_items(x, n, tt.e0 + (int64_t)w * kWaveItems, xn);
     for (int q = 0; q < tiles; ++q) {
         const int64_t e0 = tt.e0 + (int64_t)q * kTile;
         if (e0 >= n)
             break;
+        ++done_tiles;
         uint32_t xv[kItems];
-        load_items(x, n, e0 + (int64_t)w * kWaveItems, xv);
+#pragma unroll
+        for (int r = 0; r < kItems; ++r)
+            xv[r] = xn[r];
+        if (q + 1 < tiles && e0 + kTile < n)
+            load_items(x, n, e0 + kTile + (int64_t)w * kWaveItems, xn);
 #pragma unroll
         for (int r = 0; r < kItems; ++r) {
             const int64_t e = e0 + (int64_t)w * kWaveItems + (int64_t)r * kWave + __lane_id();
@@ -361,33 +413,26 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const Inst *__restrict__ 
         if (c)
             atomicAdd(&hp[b], c);
     }
-}
-
-// Chooses each node's digit of this pass from its finished histogram and
-// stores the node's state for the next pass (one workgroup per node).
-template <int D, int BITS>
-__global__ __launch_bounds__(kThreads) void k_sel_pick(const Inst *__restrict__ inst,
-                                                       const uint2 *__restrict__ node_tab, TopArrays A, int j,
-                                                       int pass) {
-    using Dg = Digit<BITS>;
-    __shared__ uint32_t s_w[kWaves];
-    __shared__ uint32_t s_pick[2];
-    TopTile tt;
-    if (!top_node(inst, node_tab, j, tt))
+    // every tile of the node is counted once; the workgroup whose tiles
+    // complete the count picks the digit
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t node_tiles = (uint32_t)((tt.g.count + kTile - 1) / kTile);
+        const uint32_t before = __hip_atomic_fetch_add(&state[tt.t].arrive, done_tiles, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+        s_last = before + done_tiles == node_tiles ? 1u : 0u;
+    }
+    __syncthreads();
+    if (s_last == 0)
         return;
-    const Inst &I = *tt.I;
-    const NodeSelect ns = node_select<D, BITS>(A.nboxes + I.B + ((1ll << j) + tt.t) * 2 * D);
-    if (pass >= ns.passes || tt.g.half == tt.g.count)
-        return;
-    SelectState *state = static_cast<SelectState *>(A.state) + I.S;
-    SelectState st = pass == 0 ? SelectState{0u, 0u, (uint32_t)tt.g.half} : state[tt.t];
-    int lo, hi;
-    digit_bits(ns.bits, pass, BITS, lo, hi);
-    pick_digit<BITS>(A.hist + I.H + hist_words_below(j, I.wbits) + (int64_t)pass * (1ll << j) * Dg::kBins +
-                         tt.t * Dg::kBins,
-                     hi - lo, st, s_w, s_pick);
-    if (threadIdx.x == 0)
-        state[tt.t] = st;
+    pick_digit<BITS>(hp, hi - lo, st, s_w, s_pick);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&state[tt.t].prefix, st.prefix, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&state[tt.t].less, st.less, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&state[tt.t].rank, st.rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&state[tt.t].match, st.match, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&state[tt.t].arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 struct NodeSplit {
@@ -416,8 +461,12 @@ __global__ __launch_bounds__(kThreads) void k_part_count(const Inst *__restrict_
     const uint32_t *nb = A.nboxes + I.B + ((1ll << j) + tt.t) * 2 * D;
     const NodeSelect ns = node_select<D, BITS>(nb);
     const bool all_left = g.half == g.count;
-    const SelectState st = (all_left || ns.passes == 0) ? SelectState{0u, 0u, (uint32_t)g.half}
-                                                        : (static_cast<const SelectState *>(A.state) + I.S)[tt.t];
+    SelectState st = {0u, 0u, (uint32_t)g.half, 0u, 0u};
+    if (!all_left && ns.passes > 0) {
+        const SelectState *state = static_cast<const SelectState *>(A.state) + I.S;
+        st.prefix = load_agent(&state[tt.t].prefix);
+        st.rank = load_agent(&state[tt.t].rank);
+    }
     // with every digit chosen, prefix is the exact median and rank its rank
     // among the points equal to it
     if (tt.e0 == g.start && threadIdx.x == 0) {
@@ -1183,11 +1232,14 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
         DPC_TRY(ws.alloc(&cnt_less, (size_t)tiles));
         DPC_TRY(ws.alloc(&cnt_eq, (size_t)tiles));
         DPC_TRY(ws.alloc(&tile_box, (size_t)tiles * 4 * D));
+        // histograms and select records (their arrival counters) start at zero
         if (hist_words > 0)
-            launch(k_fill_u32, dim3(blocks_for(hist_words, kThreads)), dim3(kThreads), 0, s, hist,
-                               hist_words, 0u);
-        launch((k_root_box<D>), dim3(blocks_for(ix.count, kThreads)), dim3(kThreads), 0, s, ix.inst,
-                           ix.count, nboxes);
+            launch(k_fill_u32, dim3(blocks_for(hist_words, kThreads)), dim3(kThreads), 0, s, hist, hist_words, 0u);
+        const int64_t state_words = sel * (int64_t)(sizeof(SelectState) / sizeof(uint32_t));
+        launch(k_fill_u32, dim3(blocks_for(state_words, kThreads)), dim3(kThreads), 0, s, (uint32_t *)state,
+               state_words, 0u);
+        launch((k_root_box<D>), dim3(blocks_for(ix.count, kThreads)), dim3(kThreads), 0, s, ix.inst, ix.count,
+               nboxes);
         TopArrays A{XA, np, nboxes, hist, state, splits};
         uint32_t *Iin = IA, *Xout = XB, *Iout = IB;  // level j reads buffer j mod 2
         const unsigned grid = (unsigned)tiles;
@@ -1211,30 +1263,26 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
                 nt = d_nodes + node_first[j];
                 ngrid = (unsigned)(node_first[j + 1] - node_first[j]);
             }
-            for (int p = 0; p < passes; ++p) {
-                if (hgrid > 0) {
-                    if (bits == 11)
-                        launch((k_sel_hist<D, 11>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst,
-                                           ix.tile_inst, hb, per, A, j, p);
-                    else
-                        launch((k_sel_hist<D, 8>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst,
-                                           ix.tile_inst, hb, per, A, j, p);
-                }
+            for (int p = 0; p < passes && hgrid > 0; ++p) {
                 if (bits == 11)
-                    launch((k_sel_pick<D, 11>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, p);
+                    launch((k_sel_hist<D, 11>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, hb, per,
+                           A, j, p);
                 else
-                    launch((k_sel_pick<D, 8>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, p);
+                    launch((k_sel_hist<D, 8>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, hb, per,
+                           A, j, p);
             }
             if (bits == 11)
-                launch((k_part_count<C, D, 11>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst,
-                                   A, j, cnt_less, cnt_eq, box, ix.rbox, ix.split);
+                launch((k_part_count<C, D, 11>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, A, j,
+                       cnt_less, cnt_eq, box, ix.rbox, ix.split);
             else
-                launch((k_part_count<C, D, 8>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst,
-                                   A, j, cnt_less, cnt_eq, box, ix.rbox, ix.split);
+                launch((k_part_count<C, D, 8>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, A, j,
+                       cnt_less, cnt_eq, box, ix.rbox, ix.split);
             launch(k_part_scan, dim3(2), dim3(kScanThreads), 0, s, cnt_less, cnt_eq, (int)tiles);
-            launch((k_part_scatter<D>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, A, Iin,
-                               Xout, Iout, j, cnt_less, cnt_eq, tile_box);
-            launch((k_box_reduce<D>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j, tile_box);
+            launch((k_part_scatter<D>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, A,
+                   (const uint32_t *)Iin, Xout, Iout, j, (const uint32_t *)cnt_less, (const uint32_t *)cnt_eq,
+                   tile_box);
+            launch((k_box_reduce<D>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j,
+                   (const uint32_t *)tile_box);
             DPC_HIP(hipGetLastError());
             uint32_t *t = A.X;
             A.X = Xout;

@@ -441,17 +441,18 @@ def planned(torch, dpc, pool, pts, calls: int = 200) -> dict:
     return res
 
 
-def fenwick(torch, dpc, inst, P, want, runs: int = 3) -> dict:
-    """The whole method with the Fenwick-tree dependent backend on the
-    headline workload (per-step GPU times from HIP events), outputs compared
-    with the priority-search tree's."""
-    got = dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, fenwick=True)
+def backend(torch, dpc, inst, P, want, runs: int = 3, **which) -> dict:
+    """The whole method with another dependent-point backend (fenwick=True:
+    the Fenwick tree of Algorithm 2; pst=True: the priority-search k-d tree
+    with one point per node) on the headline workload (per-step GPU times from
+    HIP events), outputs compared with the default k-d tree's."""
+    got = dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, **which)
     torch.cuda.synchronize()
     same = all(torch.equal(a, b) for a, b in zip(got, want))
     total, dep = [], []
     for _ in range(runs):
         t0 = time.perf_counter()
-        dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, out=got, fenwick=True, time_stages=True)
+        dpc.run(P, inst.d_cut, inst.rho_min, inst.delta_min, out=got, time_stages=True, **which)
         st = dpc.last_stats()["stage_ms"]
         torch.cuda.synchronize()
         total.append((time.perf_counter() - t0) * 1000.0)
@@ -460,7 +461,7 @@ def fenwick(torch, dpc, inst, P, want, runs: int = 3) -> dict:
     dep.sort()
     return {"workload": inst.name, "runs": runs, "ms_per_step": total[len(total) // 2],
             "dependent_ms": dep[len(dep) // 2], "points_per_s": inst.n / (total[len(total) // 2] / 1000.0),
-            "outputs_identical_to_priority_tree": bool(same)}
+            "outputs_identical_to_default_tree": bool(same)}
 
 
 def transfers(torch, inst, ms_step: float, reps: int = 5) -> dict:
@@ -505,7 +506,8 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--no-config2", action="store_true", help="skip the 10M-point 3-D and 8-D workloads")
     ap.add_argument("--config2-steps", type=int, default=5)
-    ap.add_argument("--no-fenwick", action="store_true", help="skip the Fenwick-backend measurement")
+    ap.add_argument("--no-fenwick", action="store_true",
+                    help="skip the measurements of the other dependent-point backends")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-workload measurement")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -595,8 +597,11 @@ def main() -> int:
             rec["config2"][name] = single_workload(torch, dpc, datagen, name, args.config2_steps, 1)
     if not args.no_fenwick:
         print("bench: Fenwick-tree dependent backend", file=sys.stderr, flush=True)
-        rec["fenwick"] = fenwick(torch, dpc, inst, P, out)
-        rec["fenwick"]["priority_tree_dependent_ms"] = stage_ms["priority"] + stage_ms["dependent"]
+        rec["fenwick"] = backend(torch, dpc, inst, P, out, fenwick=True)
+        rec["fenwick"]["default_tree_dependent_ms"] = stage_ms["priority"] + stage_ms["dependent"]
+        print("bench: priority-search k-d tree dependent backend", file=sys.stderr, flush=True)
+        rec["priority_search_tree"] = backend(torch, dpc, inst, P, out, pst=True)
+        rec["priority_search_tree"]["default_tree_dependent_ms"] = stage_ms["priority"] + stage_ms["dependent"]
     if not args.no_batch:
         print("bench: batched workload", file=sys.stderr, flush=True)
         rec["batched"] = batched(torch, dpc, datagen, args.batch_steps)

@@ -94,6 +94,12 @@ typedef enum {
  * (Section 4.2).  Same outputs; a different algorithm, for comparison.
  * Work counters (DPC_COUNT_WORK) then cover the density step only. */
 #define DPC_FENWICK_DEPENDENTS 8u
+/* dpc_run flag: find dependent points with the priority-search k-d tree
+ * exactly as Section 4.2 defines it, every node storing the point of highest
+ * priority in its subtree (DPC_BACKEND_PRIORITY_SEARCH_TREE below).  Same
+ * outputs; not combinable with DPC_FENWICK_DEPENDENTS.  Work counters then
+ * cover the density step only. */
+#define DPC_PST_DEPENDENTS 16u
 
 /* Steps of dpc_run timed by DPC_TIME_STAGES. */
 enum {
@@ -165,8 +171,8 @@ DPC_API int dpc_cluster(int64_t n, const int32_t *rho, const int32_t *dep, const
 /*
  * The whole method: density, dependent points and labels, sharing one
  * spatial index (the three steps of Section 1).  flags: any combination of
- * DPC_SKIP_NOISE_DEPENDENTS, DPC_TIME_STAGES, DPC_COUNT_WORK and
- * DPC_FENWICK_DEPENDENTS.  Output
+ * DPC_SKIP_NOISE_DEPENDENTS, DPC_TIME_STAGES, DPC_COUNT_WORK and one of
+ * DPC_FENWICK_DEPENDENTS and DPC_PST_DEPENDENTS.  Output
  * arrays as above; all four are written.
  */
 DPC_API int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,
@@ -432,23 +438,34 @@ DPC_API int dpc_autotune(const int32_t *points, int64_t n, int32_t d, double d_c
                          double delta_min, hipStream_t stream, double *ms_out, int32_t *chosen);
 
 /*
- * Dependent-point backend per dimension: the priority-search k-d tree
- * (Section 4.2, the default) or the Fenwick tree of k-d trees (Section 5,
- * Algorithm 2).  Both give the same outputs.  dpc_run uses the Fenwick tree
- * when the setting for d says so or DPC_FENWICK_DEPENDENTS is passed; the
- * other calls always use the priority-search tree.  The setting is
- * process-wide.
+ * Dependent-point backend per dimension.  All give the same outputs.
+ *   DPC_BACKEND_PRIORITY_TREE (the default): the priority nearest-neighbour
+ *     search of Section 4.2.2 on a balanced k-d tree whose nodes carry the
+ *     highest priority below them (points stay in the leaves); the fastest
+ *     here, and the only one the batched, served, planned and
+ *     allocation-free calls use.
+ *   DPC_BACKEND_FENWICK: the Fenwick tree of k-d trees (Section 5,
+ *     Algorithm 2).
+ *   DPC_BACKEND_PRIORITY_SEARCH_TREE: the priority-search k-d tree exactly as
+ *     Section 4.2 defines it, every node storing the point of highest
+ *     priority in its subtree and the rest split below it (Algorithm 1).
+ * dpc_run uses the backend set for d unless DPC_FENWICK_DEPENDENTS or
+ * DPC_PST_DEPENDENTS is passed; dpc_dependent and the other calls always use
+ * DPC_BACKEND_PRIORITY_TREE.  The setting is process-wide.
  * dpc_set_dependent_backend: DPC_ERR_INVALID_ARG for d outside [1, 8] or an
  *   unknown backend.
  * dpc_dependent_backend: the current backend for d (-1 for an invalid d).
  * dpc_autotune_dependent: runs the whole method on the given instance with
  *   each backend (one warm-up and two timed runs each, HIP events on
- *   `stream`), keeps the faster one for dimension d and returns the times in
- *   ms_out[DPC_BACKEND_*] and the choice in *chosen (either may be NULL).
- *   Arguments as for dpc_autotune.  Synchronises the stream.
+ *   `stream`), keeps the fastest for dimension d and returns the times in
+ *   ms_out[DPC_BACKEND_*] (DPC_BACKENDS entries) and the choice in *chosen
+ *   (either may be NULL).  Arguments as for dpc_autotune.  Synchronises the
+ *   stream.
  */
 #define DPC_BACKEND_PRIORITY_TREE 0
 #define DPC_BACKEND_FENWICK 1
+#define DPC_BACKEND_PRIORITY_SEARCH_TREE 2
+#define DPC_BACKENDS 3
 DPC_API int dpc_set_dependent_backend(int32_t d, int32_t backend);
 DPC_API int32_t dpc_dependent_backend(int32_t d);
 DPC_API int dpc_autotune_dependent(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min,

@@ -19,7 +19,9 @@ SKIP_NOISE_DEPENDENTS = 1
 TIME_STAGES = 2
 COUNT_WORK = 4
 FENWICK_DEPENDENTS = 8
-BACKENDS = ("priority_tree", "fenwick")  # DPC_BACKEND_PRIORITY_TREE, DPC_BACKEND_FENWICK
+PST_DEPENDENTS = 16
+# DPC_BACKEND_PRIORITY_TREE, DPC_BACKEND_FENWICK, DPC_BACKEND_PRIORITY_SEARCH_TREE
+BACKENDS = ("priority_tree", "fenwick", "priority_search_tree")
 INF = (1 << 63) - 1
 STAGES = ("index", "density", "priority", "dependent", "labels")
 
@@ -264,13 +266,15 @@ def last_stats() -> dict:
 
 
 def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool = False, out=None,
-        stream=None, time_stages: bool = False, count_work: bool = False, fenwick: bool = False):
+        stream=None, time_stages: bool = False, count_work: bool = False, fenwick: bool = False,
+        pst: bool = False):
     """(rho, dep, delta2, label) of the whole method on device points.
 
     time_stages / count_work record per-step GPU times / work counters of
     this call for last_stats() (measurement only).  fenwick finds the
-    dependent points with the Fenwick tree of k-d trees instead of the
-    priority-search k-d tree (same outputs)."""
+    dependent points with the Fenwick tree of k-d trees, pst with the
+    priority-search k-d tree that stores one point per node, instead of the
+    default k-d tree (same outputs)."""
     torch = _torch()
     n, d = _check_points(points)
     dev = points.device
@@ -281,7 +285,8 @@ def run(points, d_cut: float, rho_min: int, delta_min: float, skip_noise: bool =
     delta2 = _out(out[2], n, torch.int64, dev)
     label = _out(out[3], n, torch.int32, dev)
     flags = (SKIP_NOISE_DEPENDENTS if skip_noise else 0) | (TIME_STAGES if time_stages else 0) \
-        | (COUNT_WORK if count_work else 0) | (FENWICK_DEPENDENTS if fenwick else 0)
+        | (COUNT_WORK if count_work else 0) | (FENWICK_DEPENDENTS if fenwick else 0) \
+        | (PST_DEPENDENTS if pst else 0)
     st = load().dpc_run(_ptr(points), n, d, float(d_cut), int(rho_min), float(delta_min), flags, _ptr(rho),
                         _ptr(dep), _ptr(delta2), _ptr(label), _stream(stream))
     if st != OK:
@@ -601,13 +606,13 @@ def dependent_backend(d: int) -> str:
 
 
 def autotune_dependent(points, d_cut: float, rho_min: int, delta_min: float, stream=None) -> dict:
-    """Times both dependent-point backends on this instance and keeps the
-    faster for its dimension; returns {"ms": {backend: t}, "chosen": backend}."""
+    """Times every dependent-point backend on this instance and keeps the
+    fastest for its dimension; returns {"ms": {backend: t}, "chosen": backend}."""
     n, d = _check_points(points)
-    ms = (ctypes.c_double * 2)()
+    ms = (ctypes.c_double * len(BACKENDS))()
     ch = ctypes.c_int32()
     st = load().dpc_autotune_dependent(_ptr(points), n, d, float(d_cut), int(rho_min), float(delta_min),
                                        _stream(stream), ms, ctypes.byref(ch))
     if st != OK:
         raise DPCError(st, "dpc_autotune_dependent")
-    return {"ms": {BACKENDS[0]: ms[0], BACKENDS[1]: ms[1]}, "chosen": BACKENDS[ch.value]}
+    return {"ms": {b: ms[i] for i, b in enumerate(BACKENDS)}, "chosen": BACKENDS[ch.value]}

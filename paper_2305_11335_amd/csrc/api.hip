@@ -259,8 +259,10 @@ dpc_status make_job(const int32_t *points, int64_t n, int32_t d, double d_cut, i
 
 // The whole method on one group (instances of one dimension and one
 // arithmetic), every step once for all of them.
+// backend: DPC_BACKEND_* (the Fenwick tree and the priority-search tree
+// serve single instances; groups always use the k-d tree).
 dpc_status run_group(const std::vector<Job> &jobs, int d, Arith arith, RunRecorder *rec, int64_t *counters,
-                     Workspace &ws, bool fenwick = false) {
+                     Workspace &ws, int backend = DPC_BACKEND_PRIORITY_TREE) {
     hipStream_t stream = ws.stream;
     Index ix;
     DPC_TRY(build_group(jobs, d, arith, leaf_log2(d), ws, ix));
@@ -271,11 +273,16 @@ dpc_status run_group(const std::vector<Job> &jobs, int d, Arith arith, RunRecord
     DPC_TRY(launch_density(ix, srho, counters, stream));
     if (rec)
         DPC_TRY(rec->mark(DPC_STAGE_DENSITY));
-    if (fenwick && ix.count == 1) {
+    if (backend == DPC_BACKEND_FENWICK && ix.count == 1) {
         // the Fenwick tree of Algorithm 2 orders the points by priority itself
         if (rec)
             DPC_TRY(rec->mark(DPC_STAGE_PRIORITY));
         DPC_TRY(fenwick_dependent(jobs[0], d, arith, ix.lsh, ws));
+    } else if (backend == DPC_BACKEND_PRIORITY_SEARCH_TREE && ix.count == 1) {
+        // the priority-search tree of Section 4.2 is built from the priorities
+        if (rec)
+            DPC_TRY(rec->mark(DPC_STAGE_PRIORITY));
+        DPC_TRY(pst_dependent(jobs[0], d, ws));
     } else {
         DPC_TRY(build_priority(srho, false, ws, ix));
         if (rec)
@@ -462,7 +469,7 @@ std::atomic<int> g_backend[kMaxDim + 1] = {};
 // run, then the faster of two, timed with HIP events on the stream; the
 // outputs go to workspace.
 dpc_status time_choice(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
-                       bool fenwick, hipStream_t stream, float *best_ms) {
+                       int backend, hipStream_t stream, float *best_ms) {
     Job J;
     int32_t *rho, *dep, *label;
     int64_t *delta2;
@@ -488,7 +495,7 @@ dpc_status time_choice(const int32_t *points, int64_t n, int32_t d, double d_cut
         if (st == DPC_OK)
             st = job_bounds(jobs, d, run_ws, nullptr);
         if (st == DPC_OK)
-            st = run_group(jobs, d, job_arith(jobs[0], d), nullptr, nullptr, run_ws, fenwick);
+            st = run_group(jobs, d, job_arith(jobs[0], d), nullptr, nullptr, run_ws, backend);
         if (st == DPC_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
             st = DPC_ERR_HIP;
         float ms = 0.0f;
@@ -677,8 +684,9 @@ int dpc_cluster_sweep(int64_t n, const int32_t *rho, const int32_t *dep, const i
 
 int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t rho_min, double delta_min,
             uint32_t flags, int32_t *rho, int32_t *dep, int64_t *delta2, int32_t *label, hipStream_t stream) {
-    const uint32_t known = DPC_SKIP_NOISE_DEPENDENTS | DPC_TIME_STAGES | DPC_COUNT_WORK | DPC_FENWICK_DEPENDENTS;
-    if (flags & ~known)
+    const uint32_t known =
+        DPC_SKIP_NOISE_DEPENDENTS | DPC_TIME_STAGES | DPC_COUNT_WORK | DPC_FENWICK_DEPENDENTS | DPC_PST_DEPENDENTS;
+    if ((flags & ~known) || ((flags & DPC_FENWICK_DEPENDENTS) && (flags & DPC_PST_DEPENDENTS)))
         return DPC_ERR_INVALID_ARG;
     Job J;
     DPC_TRY(make_job(points, n, d, d_cut, rho_min, delta_min, flags, rho, dep, delta2, label, J));
@@ -695,8 +703,10 @@ int dpc_run(const int32_t *points, int64_t n, int32_t d, double d_cut, int32_t r
     }
     std::vector<Job> jobs{J};
     DPC_TRY(job_bounds(jobs, d, ws, nullptr));
-    const bool fenwick = (flags & DPC_FENWICK_DEPENDENTS) || g_backend[d].load(std::memory_order_relaxed) == DPC_BACKEND_FENWICK;
-    DPC_TRY(run_group(jobs, d, job_arith(jobs[0], d), &rec, counters, ws, fenwick));
+    const int backend = (flags & DPC_FENWICK_DEPENDENTS)   ? DPC_BACKEND_FENWICK
+                        : (flags & DPC_PST_DEPENDENTS)     ? DPC_BACKEND_PRIORITY_SEARCH_TREE
+                                                           : g_backend[d].load(std::memory_order_relaxed);
+    DPC_TRY(run_group(jobs, d, job_arith(jobs[0], d), &rec, counters, ws, backend));
     if (counters)
         DPC_TRY(rec.read_counters(counters));
     rec.commit(ws.bytes);
@@ -762,7 +772,7 @@ int dpc_autotune(const int32_t *points, int64_t n, int32_t d, double d_cut, int3
     dpc_status st = DPC_OK;
     for (int c = 0; c < 2 && st == DPC_OK; ++c) {
         set_leaf_log2(d, kMinLeafLog2 + c);
-        st = time_choice(points, n, d, d_cut, rho_min, delta_min, false, stream, &best_ms[c]);
+        st = time_choice(points, n, d, d_cut, rho_min, delta_min, DPC_BACKEND_PRIORITY_TREE, stream, &best_ms[c]);
     }
     if (st != DPC_OK) {
         set_leaf_log2(d, before);
@@ -780,7 +790,7 @@ int dpc_autotune(const int32_t *points, int64_t n, int32_t d, double d_cut, int3
 }
 
 int dpc_set_dependent_backend(int32_t d, int32_t backend) {
-    if (d < 1 || d > kMaxDim || (backend != DPC_BACKEND_PRIORITY_TREE && backend != DPC_BACKEND_FENWICK))
+    if (d < 1 || d > kMaxDim || backend < DPC_BACKEND_PRIORITY_TREE || backend >= DPC_BACKENDS)
         return DPC_ERR_INVALID_ARG;
     g_backend[d].store(backend, std::memory_order_relaxed);
     return DPC_OK;
@@ -796,16 +806,17 @@ int dpc_autotune_dependent(const int32_t *points, int64_t n, int32_t d, double d
                            double delta_min, hipStream_t stream, double *ms_out, int32_t *chosen) {
     if (bad_shape(n, d) || n == 0 || points == nullptr)
         return DPC_ERR_INVALID_ARG;
-    float best_ms[2] = {0.0f, 0.0f};
-    for (int c = 0; c < 2; ++c)
-        DPC_TRY(time_choice(points, n, d, d_cut, rho_min, delta_min, c == DPC_BACKEND_FENWICK, stream, &best_ms[c]));
-    const int pick = best_ms[DPC_BACKEND_FENWICK] < best_ms[DPC_BACKEND_PRIORITY_TREE] ? DPC_BACKEND_FENWICK
-                                                                                     : DPC_BACKEND_PRIORITY_TREE;
-    g_backend[d].store(pick, std::memory_order_relaxed);
-    if (ms_out) {
-        ms_out[0] = best_ms[0];
-        ms_out[1] = best_ms[1];
+    float best_ms[DPC_BACKENDS] = {};
+    int pick = DPC_BACKEND_PRIORITY_TREE;
+    for (int c = 0; c < DPC_BACKENDS; ++c) {
+        DPC_TRY(time_choice(points, n, d, d_cut, rho_min, delta_min, c, stream, &best_ms[c]));
+        if (best_ms[c] < best_ms[pick])
+            pick = c;
     }
+    g_backend[d].store(pick, std::memory_order_relaxed);
+    if (ms_out)
+        for (int c = 0; c < DPC_BACKENDS; ++c)
+            ms_out[c] = best_ms[c];
     if (chosen)
         *chosen = pick;
     return DPC_OK;

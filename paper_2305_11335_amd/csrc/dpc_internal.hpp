@@ -315,6 +315,20 @@ dpc_status priority_levels(Index &ix, hipStream_t s);
 // writes the job's dep and delta2.  Results equal launch_dependent's.
 dpc_status fenwick_dependent(const Job &J, int d, Arith arith, int lsh, Workspace &ws);
 
+// radix.hip: stable sort of n (key, value) pairs by key bits [0, bits),
+// ascending, ping-ponging between (keys, vals) and (keys_alt, vals_alt);
+// *keys_out / *vals_out receive whichever pair holds the result.  Takes its
+// histograms from ws.  K is uint32_t or uint64_t.
+template <typename K>
+dpc_status radix_sort_pairs(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, int64_t n, int bits,
+                            Workspace &ws, K **keys_out, uint32_t **vals_out);
+
+// Dependent points of one instance through the priority-search k-d tree of
+// Section 4.2 (one point stored per node), from the rho array the job holds
+// (input order); writes the job's dep and delta2.  Results equal
+// launch_dependent's.
+dpc_status pst_dependent(const Job &J, int d, Workspace &ws);
+
 // Allocates the group's descriptors (and tile table) and copies them to the
 // device (synchronising the stream).
 dpc_status upload_group(Workspace &ws, Index &ix);

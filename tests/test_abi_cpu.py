@@ -122,7 +122,7 @@ def test_argument_errors_before_any_device_work():
     assert _call("dpc_run", fake, 5, 2, float("nan"), 0, 1.0, 0, fake, fake, fake, fake, NULL) == E
     assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 0, fake, fake, NULL, fake, NULL) == E
     assert _call("dpc_run", fake, 5, 0, 1.0, 0, 1.0, 0, fake, fake, fake, fake, NULL) == E
-    assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 16, fake, fake, fake, fake, NULL) == E
+    assert _call("dpc_run", fake, 5, 2, 1.0, 0, 1.0, 32, fake, fake, fake, fake, NULL) == E
     assert _call("dpc_run", fake, 5, 0, 1.0, 0, 1.0, 8, fake, fake, fake, fake, NULL) == E  # Fenwick flag, bad d
     assert dpc.load().dpc_last_stats(None) == E
     assert _call("dpc_batch_run", None, 3, 0, NULL) == E
@@ -276,7 +276,13 @@ def test_dependent_backend_setting_is_host_only():
     lib = dpc.load()
     E = dpc._binding.ERR_INVALID_ARG
     assert lib.dpc_set_dependent_backend(0, 0) == E and lib.dpc_set_dependent_backend(9, 1) == E
-    assert lib.dpc_set_dependent_backend(2, 2) == E and lib.dpc_set_dependent_backend(2, -1) == E
+    assert lib.dpc_set_dependent_backend(2, 3) == E and lib.dpc_set_dependent_backend(2, -1) == E
+    dpc.set_dependent_backend(5, "priority_search_tree")
+    assert dpc.dependent_backend(5) == "priority_search_tree"
+    dpc.set_dependent_backend(5, "priority_tree")
+    # the two alternative-backend flags of dpc_run exclude each other (checked on the host)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.dpc_run(fake, 10, 2, 1.0, 0, 1.0, 8 | 16, fake, fake, fake, fake, NULL) == E
     assert lib.dpc_dependent_backend(0) == -1 and lib.dpc_dependent_backend(9) == -1
     with pytest.raises(ValueError):
         dpc.set_dependent_backend(2, "grid")

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kThreads) void k_parent(int64_t n, const int32_t *_
 }
 
 __global__ __launch_bounds__(kThreads) void k_roots(int64_t n, const int32_t *__restrict__ rho, int32_t rho_min,
-                                                    int32_t *par, int32_t *__restrict__ label, int32_t *flag) {
+                                                    int32_t *par, int32_t *__restrict__ label) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
@@ -58,12 +58,10 @@ __global__ __launch_bounds__(kThreads) void k_roots(int64_t n, const int32_t *__
         return;
     }
     int32_t x = (int32_t)i;
-    // a chain of strictly rising priorities has fewer than n edges
-    for (int64_t steps = 0;; ++steps) {
-        if (steps > n) {
-            __hip_atomic_store(flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-        }
+    // every followed edge rises (checked, or produced by the library's own
+    // dependent step), so a chain has fewer than n edges; the bound only
+    // keeps a walk finite
+    for (int64_t steps = 0; steps <= n; ++steps) {
         const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (p == x)
             break;
@@ -222,7 +220,7 @@ dpc_status launch_cluster(int64_t n, const int32_t *rho, const int32_t *dep, con
         if (h != 0)
             return DPC_ERR_NOT_FOREST;
     }
-    launch(k_roots, grid, block, 0, s, n, rho, rho_min, par, label, flag);
+    launch(k_roots, grid, block, 0, s, n, rho, rho_min, par, label);
     DPC_HIP(hipGetLastError());
     return DPC_OK;
 }

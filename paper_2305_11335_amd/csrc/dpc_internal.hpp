@@ -37,6 +37,12 @@ constexpr int kMinLeafLog2 = 4;
 constexpr int kMaxLeafLog2 = 5;
 constexpr int kTile = 2048;    // positions per tile (the unit of the top-level build passes)
 
+// Digit width of the radix select of top build level j (whose 2^j nodes each
+// keep one histogram of 2^bits counts per pass): 11 bits while a level has
+// at most 256 nodes, 10 up to 4096 nodes (two passes for coordinates of up to
+// 20 bits), 8 below (small histograms for many nodes).
+__host__ __device__ inline int top_level_bits(int j) { return j <= 8 ? 11 : (j <= 12 ? 10 : 8); }
+
 // Coordinates and squared distances are exact in double when every squared
 // distance stays below 2^53 (the "f64" path); otherwise 64-bit integers.
 enum class Arith { F64, I64 };

@@ -472,7 +472,7 @@ uint64_t workspace_bound(int64_t n, int d) {
     // top levels: node boxes, histograms (widest coordinates: 32 bits), select records
     b += (2ull << jb) * 2 * D * 4;
     for (int l = 0; l < jb; ++l) {
-        const int bits = l <= 8 ? 11 : 8;
+        const int bits = top_level_bits(l);
         b += (uint64_t)((32 + bits - 1) / bits) * (1ull << l) * (1ull << bits) * 4;
     }
     b += (jb > 0 ? 1ull << (jb - 1) : 0) * 32;
@@ -523,7 +523,7 @@ dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, int lsh
         L += 1ll << I.height;
         int64_t hw = 0;
         for (int l = 0; l < I.jb; ++l) {
-            const int bits = l <= 8 ? 11 : 8;  // the digit width of top level l
+            const int bits = top_level_bits(l);
             hw += (int64_t)((I.wbits + bits - 1) / bits) * (1ll << l) * (1ll << bits);
         }
         H += hw;

@@ -8,8 +8,9 @@
 // the global minimum, as uint32, plus the id).  A node's median along its
 // split axis is found exactly by most-significant-digit radix select: each
 // pass histograms one digit of the points that still match the digits found
-// so far (11-bit digits while a level has few nodes, 8-bit below), and the
-// workgroup whose tiles complete a node's histogram picks the node's digit.
+// so far (11-bit digits while a level has few nodes, 10-bit and then 8-bit
+// below), and the workgroup whose tiles complete a node's histogram picks the
+// node's digit.
 // The node is then partitioned stably: "less than the median" and "equal to
 // the median" flags are counted per tile and scanned, and the first equal
 // points in array order fill the left half.  The same pass reduces the
@@ -150,11 +151,7 @@ __device__ inline NodeGeom node_geom(int64_t t, int64_t S, int64_t n) {
     return g;
 }
 
-// Digit width of a top level: 11 bits while the level has at most 256 nodes
-// (fewer passes), 8 bits below (small histograms for many nodes).
-constexpr int kWideLevels = 8;
-
-__host__ __device__ inline int level_bits(int j) { return j <= kWideLevels ? 11 : 8; }
+__host__ __device__ inline int level_bits(int j) { return top_level_bits(j); }
 
 // Words of an instance's histograms of levels [0, j): passes x nodes x bins.
 __host__ __device__ inline int64_t hist_words_below(int j, int wbits) {
@@ -1267,12 +1264,18 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
                 if (bits == 11)
                     launch((k_sel_hist<D, 11>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, hb, per,
                            A, j, p);
+                else if (bits == 10)
+                    launch((k_sel_hist<D, 10>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, hb, per,
+                           A, j, p);
                 else
                     launch((k_sel_hist<D, 8>), dim3(hgrid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, hb, per,
                            A, j, p);
             }
             if (bits == 11)
                 launch((k_part_count<C, D, 11>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, A, j,
+                       cnt_less, cnt_eq, box, ix.rbox, ix.split);
+            else if (bits == 10)
+                launch((k_part_count<C, D, 10>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, A, j,
                        cnt_less, cnt_eq, box, ix.rbox, ix.split);
             else
                 launch((k_part_count<C, D, 8>), dim3(grid), dim3(kThreads), 0, s, ix.inst, ix.tile_inst, A, j,

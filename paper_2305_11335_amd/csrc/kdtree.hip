@@ -760,6 +760,39 @@ __global__ __launch_bounds__(kThreads) void k_soa_init(const Inst *__restrict__ 
     Ids[pos] = (uint32_t)i;
 }
 
+// Minimum and maximum over groups of 2^G consecutive lanes (G = 4, 5 or 6)
+// with DPP lane moves, which run on the vector ALU instead of the LDS
+// crossbar: pairs and quads within a quad, then the mirrored halves of each
+// 8- and 16-lane row; rows then pass their last lane's value on (row 1 from
+// row 0, row 3 from row 2, then rows 2 and 3 from lane 31).  The result is in
+// every lane of a 16-lane group and in the last lane of a 32- or 64-lane one.
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp_move(uint32_t v, uint32_t keep) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)keep, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+template <int G>
+__device__ inline void group_min_max(uint32_t &mn, uint32_t &mx) {
+    static_assert(G >= 4 && G <= 6, "groups of 16, 32 or 64 lanes");
+    uint32_t t;
+#define DPC_MINMAX_STEP(CTRL, ROWS)                                      \
+    t = dpp_move<CTRL, ROWS>(mn, 0xFFFFFFFFu);                           \
+    mn = t < mn ? t : mn;                                                \
+    t = dpp_move<CTRL, ROWS>(mx, 0u);                                    \
+    mx = t > mx ? t : mx;
+    DPC_MINMAX_STEP(0xB1, 0xF)   // quad_perm [1,0,3,2]
+    DPC_MINMAX_STEP(0x4E, 0xF)   // quad_perm [2,3,0,1]
+    DPC_MINMAX_STEP(0x141, 0xF)  // row_half_mirror
+    DPC_MINMAX_STEP(0x140, 0xF)  // row_mirror
+    if constexpr (G >= 5) {
+        DPC_MINMAX_STEP(0x142, 0xA)  // row_bcast:15 into rows 1 and 3
+    }
+    if constexpr (G >= 6) {
+        DPC_MINMAX_STEP(0x143, 0xC)  // row_bcast:31 into rows 2 and 3
+    }
+#undef DPC_MINMAX_STEP
+}
+
 // ---------------------------------------------------------------------------
 // bottom levels: one workgroup per subtree, in LDS
 
@@ -830,22 +863,64 @@ __global__ __launch_bounds__(kThreads) void k_bottom(const Inst *__restrict__ in
                 s_box[u][k][1] = 0u;
             }
         __syncthreads();
-        // boxes: every leaf-sized group of points lies inside one node
-        for (int base = w * kWave; base < cnt0; base += kThreads) {
-            const int i = base + lane;
-            const bool have = i < cnt0;
+        // boxes: each wave takes a contiguous share of the points and
+        // reduces each node's part of it once (nodes are aligned runs of S
+        // points, so a share holds whole nodes or lies inside one)
+        {
+            constexpr int PW = M / kWaves;  // points per wave
+            const int i0 = w * PW;
+            if (S >= kWave) {
+                // one node per run of min(S, PW) points: lanes gather its
+                // 64-point chunks, then one reduction across the wave
+                const int run = S < PW ? S : PW;
+                for (int r0 = i0; r0 < i0 + PW && r0 < cnt0; r0 += run) {
+                    uint32_t mn[D], mx[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                uint32_t a = have ? s_x[k][i] : 0xFFFFFFFFu;
-                uint32_t b = have ? s_x[k][i] : 0u;
-                for (int o = 1 << (lsh - 1); o > 0; o >>= 1) {
-                    const uint32_t ta = __shfl_xor(a, o, kWave), tb = __shfl_xor(b, o, kWave);
-                    a = ta < a ? ta : a;
-                    b = tb > b ? tb : b;
+                    for (int k = 0; k < D; ++k) {
+                        mn[k] = 0xFFFFFFFFu;
+                        mx[k] = 0u;
+                    }
+                    for (int c = r0; c < r0 + run; c += kWave) {
+                        const int i = c + lane;
+                        if (i < cnt0) {
+#pragma unroll
+                            for (int k = 0; k < D; ++k) {
+                                const uint32_t x = s_x[k][i];
+                                mn[k] = x < mn[k] ? x : mn[k];
+                                mx[k] = x > mx[k] ? x : mx[k];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        group_min_max<6>(mn[k], mx[k]);
+                        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)mn[k], kWave - 1);
+                        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)mx[k], kWave - 1);
+                        if (lane == 0) {
+                            atomicMin(&s_box[r0 / S][k][0], a);
+                            atomicMax(&s_box[r0 / S][k][1], b);
+                        }
+                    }
                 }
-                if ((i & ((1 << lsh) - 1)) == 0 && have) {
-                    atomicMin(&s_box[i / S][k][0], a);
-                    atomicMax(&s_box[i / S][k][1], b);
+            } else {
+                // leaf level: every 64-point chunk holds 64 / S leaves, one
+                // reduction per group of S lanes (its last lane holds it)
+                for (int c = i0; c < i0 + PW && c < cnt0; c += kWave) {
+                    const int i = c + lane;
+                    const bool have = i < cnt0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        uint32_t a = have ? s_x[k][i] : 0xFFFFFFFFu;
+                        uint32_t b = have ? s_x[k][i] : 0u;
+                        if (S == 16)
+                            group_min_max<4>(a, b);
+                        else
+                            group_min_max<5>(a, b);
+                        if ((i & (S - 1)) == S - 1 && i - (S - 1) < cnt0) {
+                            atomicMin(&s_box[i / S][k][0], a);
+                            atomicMax(&s_box[i / S][k][1], b);
+                        }
+                    }
                 }
             }
         }

@@ -56,14 +56,49 @@ struct Bottom {
 
 __device__ inline uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
 
-__device__ inline uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = __lane_id();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t t = __shfl_up(v, o, kWave);
-        if (lane >= o)
-            v += t;
+// Minimum and maximum over groups of 2^G consecutive lanes (G = 4, 5 or 6)
+// with DPP lane moves, which run on the vector ALU instead of the LDS
+// crossbar: pairs and quads within a quad, then the mirrored halves of each
+// 8- and 16-lane row; rows then pass their last lane's value on (row 1 from
+// row 0, row 3 from row 2, then rows 2 and 3 from lane 31).  The result is in
+// every lane of a 16-lane group and in the last lane of a 32- or 64-lane one.
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp_move(uint32_t v, uint32_t keep) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)keep, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+template <int G>
+__device__ inline void group_min_max(uint32_t &mn, uint32_t &mx) {
+    static_assert(G >= 4 && G <= 6, "groups of 16, 32 or 64 lanes");
+    uint32_t t;
+#define DPC_MINMAX_STEP(CTRL, ROWS)                                      \
+    t = dpp_move<CTRL, ROWS>(mn, 0xFFFFFFFFu);                           \
+    mn = t < mn ? t : mn;                                                \
+    t = dpp_move<CTRL, ROWS>(mx, 0u);                                    \
+    mx = t > mx ? t : mx;
+    DPC_MINMAX_STEP(0xB1, 0xF)   // quad_perm [1,0,3,2]
+    DPC_MINMAX_STEP(0x4E, 0xF)   // quad_perm [2,3,0,1]
+    DPC_MINMAX_STEP(0x141, 0xF)  // row_half_mirror
+    DPC_MINMAX_STEP(0x140, 0xF)  // row_mirror
+    if constexpr (G >= 5) {
+        DPC_MINMAX_STEP(0x142, 0xA)  // row_bcast:15 into rows 1 and 3
     }
+    if constexpr (G >= 6) {
+        DPC_MINMAX_STEP(0x143, 0xC)  // row_bcast:31 into rows 2 and 3
+    }
+#undef DPC_MINMAX_STEP
+}
+
+// Inclusive prefix sum across the wave with DPP lane moves: a doubling scan
+// within each 16-lane row (lanes before the row's start bring in 0), then
+// each row adds the total of the rows before it by row broadcasts.
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    v += dpp_move<0x111, 0xF>(v, 0u);  // row_shr:1
+    v += dpp_move<0x112, 0xF>(v, 0u);  // row_shr:2
+    v += dpp_move<0x114, 0xF>(v, 0u);  // row_shr:4
+    v += dpp_move<0x118, 0xF>(v, 0u);  // row_shr:8
+    v += dpp_move<0x142, 0xA>(v, 0u);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC>(v, 0u);  // row_bcast:31 into rows 2 and 3
     return v;
 }
 
@@ -758,39 +793,6 @@ __global__ __launch_bounds__(kThreads) void k_soa_init(const Inst *__restrict__ 
         X[(int64_t)k * positions + pos] = (uint32_t)v;
     }
     Ids[pos] = (uint32_t)i;
-}
-
-// Minimum and maximum over groups of 2^G consecutive lanes (G = 4, 5 or 6)
-// with DPP lane moves, which run on the vector ALU instead of the LDS
-// crossbar: pairs and quads within a quad, then the mirrored halves of each
-// 8- and 16-lane row; rows then pass their last lane's value on (row 1 from
-// row 0, row 3 from row 2, then rows 2 and 3 from lane 31).  The result is in
-// every lane of a 16-lane group and in the last lane of a 32- or 64-lane one.
-template <int CTRL, int ROWS>
-__device__ inline uint32_t dpp_move(uint32_t v, uint32_t keep) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)keep, (int)v, CTRL, ROWS, 0xF, false);
-}
-
-template <int G>
-__device__ inline void group_min_max(uint32_t &mn, uint32_t &mx) {
-    static_assert(G >= 4 && G <= 6, "groups of 16, 32 or 64 lanes");
-    uint32_t t;
-#define DPC_MINMAX_STEP(CTRL, ROWS)                                      \
-    t = dpp_move<CTRL, ROWS>(mn, 0xFFFFFFFFu);                           \
-    mn = t < mn ? t : mn;                                                \
-    t = dpp_move<CTRL, ROWS>(mx, 0u);                                    \
-    mx = t > mx ? t : mx;
-    DPC_MINMAX_STEP(0xB1, 0xF)   // quad_perm [1,0,3,2]
-    DPC_MINMAX_STEP(0x4E, 0xF)   // quad_perm [2,3,0,1]
-    DPC_MINMAX_STEP(0x141, 0xF)  // row_half_mirror
-    DPC_MINMAX_STEP(0x140, 0xF)  // row_mirror
-    if constexpr (G >= 5) {
-        DPC_MINMAX_STEP(0x142, 0xA)  // row_bcast:15 into rows 1 and 3
-    }
-    if constexpr (G >= 6) {
-        DPC_MINMAX_STEP(0x143, 0xC)  // row_bcast:31 into rows 2 and 3
-    }
-#undef DPC_MINMAX_STEP
 }
 
 // ---------------------------------------------------------------------------

@@ -70,12 +70,36 @@ constexpr int coop_max() {
     return D <= 4 ? 32 : kWave;
 }
 
-template <typename C>
-__device__ inline C shfl_xor_c(C v, int off) {
-    static_assert(sizeof(C) == 8, "64-bit coordinates");
-    uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = __shfl_xor((uint32_t)b, off, kWave), hi = __shfl_xor((uint32_t)(b >> 32), off, kWave);
-    return __builtin_bit_cast(C, ((uint64_t)hi << 32) | lo);
+// One step of group_lex_min: (s, l) against the pair DPP move CTRL brings in
+// (rows outside ROWS compare against the identity and keep theirs).
+template <int CTRL, int ROWS, typename C>
+__device__ inline void lex_min_step(C &s, uint32_t &l) {
+    static_assert(sizeof(C) == 8, "64-bit distances");
+    const uint64_t b = __builtin_bit_cast(uint64_t, s);
+    const uint64_t id = __builtin_bit_cast(uint64_t, std::numeric_limits<C>::max());
+    const uint32_t lo = dpp_move<CTRL, ROWS>((uint32_t)b, (uint32_t)id);
+    const uint32_t hi = dpp_move<CTRL, ROWS>((uint32_t)(b >> 32), (uint32_t)(id >> 32));
+    const uint32_t ol = dpp_move<CTRL, ROWS>(l, 0u);
+    const C os = __builtin_bit_cast(C, ((uint64_t)hi << 32) | lo);
+    const bool take = (os < s) | ((os == s) & (ol > l));
+    s = take ? os : s;
+    l = take ? ol : l;
+}
+
+// Lexicographic minimum of (D^2, index) over groups of 2^G lanes (a larger
+// low key word is a smaller index), by DPP lane moves: within quads, the
+// mirrored halves of 8- and 16-lane rows, then (G = 5) row 1 from row 0's and
+// row 3 from row 2's last lane.  The result is in every lane of a 16-lane
+// group and in the last lane of a 32-lane one.
+template <int G, typename C>
+__device__ inline void group_lex_min(C &s, uint32_t &l) {
+    static_assert(G == 4 || G == 5, "groups of 16 or 32 lanes");
+    lex_min_step<0xB1, 0xF>(s, l);   // quad_perm [1,0,3,2]
+    lex_min_step<0x4E, 0xF>(s, l);   // quad_perm [2,3,0,1]
+    lex_min_step<0x141, 0xF>(s, l);  // row_half_mirror
+    lex_min_step<0x140, 0xF>(s, l);  // row_mirror
+    if constexpr (G == 5)
+        lex_min_step<0x142, 0xA>(s, l);  // row_bcast:15 into rows 1 and 3
 }
 
 // A leaf that few lanes of the wave want.  Looping each of those lanes over
@@ -135,16 +159,9 @@ __device__ inline void leaf_coop(const C *__restrict__ coords, const uint64_t *_
         if (hm != 0) {
             C hs = hit ? s : std::numeric_limits<C>::max();
             uint32_t hl = hit ? (uint32_t)pk : 0u;
-#pragma unroll
-            for (int off = kL / 2; off > 0; off >>= 1) {
-                const C os = shfl_xor_c<C>(hs, off);
-                const uint32_t ol = __shfl_xor(hl, off, kWave);
-                const bool b = (os < hs) | ((os == hs) & (ol > hl));
-                hs = b ? os : hs;
-                hl = b ? ol : hl;
-            }
+            group_lex_min<LSH, C>(hs, hl);
             const bool any = ((hm >> (kL * grp)) & ((1ull << kL) - 1ull)) != 0;
-            if (pl == 0 && live && any) {
+            if (pl == kL - 1 && live && any) {
                 const uint32_t ql = sql[rr];
                 if ((hs < qb) | ((hs == qb) & (hl > ql))) {
                     sqb[rr] = hs;

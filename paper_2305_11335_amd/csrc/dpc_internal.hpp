@@ -37,6 +37,15 @@ constexpr int kMinLeafLog2 = 4;
 constexpr int kMaxLeafLog2 = 5;
 constexpr int kTile = 2048;    // positions per tile (the unit of the top-level build passes)
 
+// A DPP lane move (dpp_ctrl CTRL) within the rows selected by ROWS: each
+// lane of those rows takes v from its source lane; other lanes, and lanes
+// whose source lies outside their row, return keep.  DPP moves run on the
+// vector ALU, where __shfl_* goes through the LDS crossbar.
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp_move(uint32_t v, uint32_t keep) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)keep, (int)v, CTRL, ROWS, 0xF, false);
+}
+
 // Digit width of the radix select of top build level j (whose 2^j nodes each
 // keep one histogram of 2^bits counts per pass): 11 bits while a level has
 // at most 256 nodes, 10 up to 4096 nodes (two passes for coordinates of up to

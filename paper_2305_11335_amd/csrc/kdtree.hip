@@ -62,11 +62,6 @@ __device__ inline uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; 
 // 8- and 16-lane row; rows then pass their last lane's value on (row 1 from
 // row 0, row 3 from row 2, then rows 2 and 3 from lane 31).  The result is in
 // every lane of a 16-lane group and in the last lane of a 32- or 64-lane one.
-template <int CTRL, int ROWS>
-__device__ inline uint32_t dpp_move(uint32_t v, uint32_t keep) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)keep, (int)v, CTRL, ROWS, 0xF, false);
-}
-
 template <int G>
 __device__ inline void group_min_max(uint32_t &mn, uint32_t &mx) {
     static_assert(G >= 4 && G <= 6, "groups of 16, 32 or 64 lanes");

@@ -46,6 +46,59 @@ __device__ inline uint32_t dpp_move(uint32_t v, uint32_t keep) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)keep, (int)v, CTRL, ROWS, 0xF, false);
 }
 
+// Minimum and maximum over groups of 2^G consecutive lanes (G = 4, 5 or 6)
+// with DPP lane moves, which run on the vector ALU instead of the LDS
+// crossbar: pairs and quads within a quad, then the mirrored halves of each
+// 8- and 16-lane row; rows then pass their last lane's value on (row 1 from
+// row 0, row 3 from row 2, then rows 2 and 3 from lane 31).  The result is in
+// every lane of a 16-lane group and in the last lane of a 32- or 64-lane one.
+template <int G>
+__device__ inline void group_min_max(uint32_t &mn, uint32_t &mx) {
+    static_assert(G >= 4 && G <= 6, "groups of 16, 32 or 64 lanes");
+    uint32_t t;
+#define DPC_MINMAX_STEP(CTRL, ROWS)                                      \
+    t = dpp_move<CTRL, ROWS>(mn, 0xFFFFFFFFu);                           \
+    mn = t < mn ? t : mn;                                                \
+    t = dpp_move<CTRL, ROWS>(mx, 0u);                                    \
+    mx = t > mx ? t : mx;
+    DPC_MINMAX_STEP(0xB1, 0xF)   // quad_perm [1,0,3,2]
+    DPC_MINMAX_STEP(0x4E, 0xF)   // quad_perm [2,3,0,1]
+    DPC_MINMAX_STEP(0x141, 0xF)  // row_half_mirror
+    DPC_MINMAX_STEP(0x140, 0xF)  // row_mirror
+    if constexpr (G >= 5) {
+        DPC_MINMAX_STEP(0x142, 0xA)  // row_bcast:15 into rows 1 and 3
+    }
+    if constexpr (G >= 6) {
+        DPC_MINMAX_STEP(0x143, 0xC)  // row_bcast:31 into rows 2 and 3
+    }
+#undef DPC_MINMAX_STEP
+}
+
+// One step of group_max_u64: v against the value DPP move CTRL brings in.
+template <int CTRL, int ROWS>
+__device__ inline uint64_t max_step_u64(uint64_t v) {
+    const uint32_t lo = dpp_move<CTRL, ROWS>((uint32_t)v, 0u), hi = dpp_move<CTRL, ROWS>((uint32_t)(v >> 32), 0u);
+    const uint64_t o = ((uint64_t)hi << 32) | lo;
+    return o > v ? o : v;
+}
+
+// Maximum over groups of 2^G lanes (G = 4: every lane of a 16-lane row holds
+// it; G = 5 or 6: the last lane of each 32-lane half, or of the wave), with
+// the same DPP steps as group_min_max.
+template <int G>
+__device__ inline uint64_t group_max_u64(uint64_t v) {
+    static_assert(G >= 4 && G <= 6, "groups of 16, 32 or 64 lanes");
+    v = max_step_u64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v = max_step_u64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = max_step_u64<0x141, 0xF>(v);  // row_half_mirror
+    v = max_step_u64<0x140, 0xF>(v);  // row_mirror
+    if constexpr (G >= 5)
+        v = max_step_u64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    if constexpr (G >= 6)
+        v = max_step_u64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Digit width of the radix select of top build level j (whose 2^j nodes each
 // keep one histogram of 2^bits counts per pass): 11 bits while a level has
 // at most 256 nodes, 10 up to 4096 nodes (two passes for coordinates of up to

@@ -161,15 +161,11 @@ __global__ __launch_bounds__(kThreads) void k_fw_level_keys(const Inst *__restri
         key = (int64_t)o < ((int64_t)1 << b) ? pack_key(2, (int32_t)ord[p]) : pack_key(act[p] ? 1 : 0, -1);
         skey[pos] = key;
     }
+    // the leaf's maximum, by DPP lane moves, lands in its last lane
     const int lsh = I.lsh;
-    for (int off = 1 << (lsh - 1); off > 0; off >>= 1) {
-        uint32_t lo = (uint32_t)key, hi = (uint32_t)(key >> 32);
-        lo = __shfl_xor(lo, off, kWave);
-        hi = __shfl_xor(hi, off, kWave);
-        const uint64_t other = ((uint64_t)hi << 32) | lo;
-        key = other > key ? other : key;
-    }
-    if ((i & ((1 << lsh) - 1)) == 0 && i < I.n)
+    key = lsh == kMaxLeafLog2 ? group_max_u64<kMaxLeafLog2>(key) : group_max_u64<kMinLeafLog2>(key);
+    const int64_t first = i - ((1 << lsh) - 1);  // the leaf's first position
+    if ((i & ((1 << lsh) - 1)) == (1 << lsh) - 1 && first < I.n)
         maxkey[I.N + (1ll << I.height) + (i >> lsh)] = key;
 }
 

@@ -185,30 +185,6 @@ __global__ __launch_bounds__(kThreads) void k_bounds_reduce(const Inst *__restri
 // ---------------------------------------------------------------------------
 // priority keys (pack_key) and the per-node maxima
 
-// One step of group_max_u64: v against the value DPP move CTRL brings in.
-template <int CTRL, int ROWS>
-__device__ inline uint64_t max_step_u64(uint64_t v) {
-    const uint32_t lo = dpp_move<CTRL, ROWS>((uint32_t)v, 0u), hi = dpp_move<CTRL, ROWS>((uint32_t)(v >> 32), 0u);
-    const uint64_t o = ((uint64_t)hi << 32) | lo;
-    return o > v ? o : v;
-}
-
-// Maximum over groups of 2^G lanes (G = 4: every lane of a 16-lane row holds
-// it; G = 5: the last lane of each 32-lane half): within quads, the mirrored
-// halves of 8- and 16-lane rows, then row 1 from row 0's and row 3 from row
-// 2's last lane.
-template <int G>
-__device__ inline uint64_t group_max_u64(uint64_t v) {
-    static_assert(G == 4 || G == 5, "groups of 16 or 32 lanes");
-    v = max_step_u64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-    v = max_step_u64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-    v = max_step_u64<0x141, 0xF>(v);  // row_half_mirror
-    v = max_step_u64<0x140, 0xF>(v);  // row_mirror
-    if constexpr (G == 5)
-        v = max_step_u64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    return v;
-}
-
 __global__ void k_fill_u64(uint64_t *__restrict__ a, int64_t m, uint64_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m)

@@ -56,34 +56,6 @@ struct Bottom {
 
 __device__ inline uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
 
-// Minimum and maximum over groups of 2^G consecutive lanes (G = 4, 5 or 6)
-// with DPP lane moves, which run on the vector ALU instead of the LDS
-// crossbar: pairs and quads within a quad, then the mirrored halves of each
-// 8- and 16-lane row; rows then pass their last lane's value on (row 1 from
-// row 0, row 3 from row 2, then rows 2 and 3 from lane 31).  The result is in
-// every lane of a 16-lane group and in the last lane of a 32- or 64-lane one.
-template <int G>
-__device__ inline void group_min_max(uint32_t &mn, uint32_t &mx) {
-    static_assert(G >= 4 && G <= 6, "groups of 16, 32 or 64 lanes");
-    uint32_t t;
-#define DPC_MINMAX_STEP(CTRL, ROWS)                                      \
-    t = dpp_move<CTRL, ROWS>(mn, 0xFFFFFFFFu);                           \
-    mn = t < mn ? t : mn;                                                \
-    t = dpp_move<CTRL, ROWS>(mx, 0u);                                    \
-    mx = t > mx ? t : mx;
-    DPC_MINMAX_STEP(0xB1, 0xF)   // quad_perm [1,0,3,2]
-    DPC_MINMAX_STEP(0x4E, 0xF)   // quad_perm [2,3,0,1]
-    DPC_MINMAX_STEP(0x141, 0xF)  // row_half_mirror
-    DPC_MINMAX_STEP(0x140, 0xF)  // row_mirror
-    if constexpr (G >= 5) {
-        DPC_MINMAX_STEP(0x142, 0xA)  // row_bcast:15 into rows 1 and 3
-    }
-    if constexpr (G >= 6) {
-        DPC_MINMAX_STEP(0x143, 0xC)  // row_bcast:31 into rows 2 and 3
-    }
-#undef DPC_MINMAX_STEP
-}
-
 // Inclusive prefix sum across the wave with DPP lane moves: a doubling scan
 // within each 16-lane row (lanes before the row's start bring in 0), then
 // each row adds the total of the rows before it by row broadcasts.

@@ -119,22 +119,6 @@ __device__ inline void node_scan(const Level &A, int64_t cap, int64_t s, int64_t
 }
 
 template <int D>
-__device__ inline void wave_reduce(uint64_t &kmax, uint32_t (&mn)[D], uint32_t (&mx)[D]) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)kmax, o, kWave), hi = __shfl_xor((uint32_t)(kmax >> 32), o, kWave);
-        const uint64_t other = ((uint64_t)hi << 32) | lo;
-        kmax = other > kmax ? other : kmax;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const uint32_t a = __shfl_xor(mn[k], o, kWave), b = __shfl_xor(mx[k], o, kWave);
-            mn[k] = a < mn[k] ? a : mn[k];
-            mx[k] = b > mx[k] ? b : mx[k];
-        }
-    }
-}
-
-template <int D>
 __device__ inline void store_node(const Tree &T, int64_t v, uint64_t kmax, const uint32_t (&mn)[D],
                                   const uint32_t (&mx)[D]) {
     T.key[v] = kmax;
@@ -145,44 +129,13 @@ __device__ inline void store_node(const Tree &T, int64_t v, uint64_t kmax, const
     }
 }
 
-// Step (1) for the nodes of depth l.  MODE 0: one workgroup per node; 1: one
+// Step (1) for the nodes of depth l whose subtrees are small.  MODE 1: one
 // wavefront per node; 2: one thread per node.
 template <int D, int MODE>
 __global__ __launch_bounds__(kThreads) void k_pst_reduce(Level A, int64_t cap, Shape sh, int l, Tree T) {
     const int64_t first = 1ll << l;
     const int64_t count = (l == sh.h ? sh.n + 1 : 2 * first) - first;
-    if constexpr (MODE == 0) {
-        __shared__ uint64_t s_k[kThreads / kWave];
-        __shared__ uint32_t s_mn[kThreads / kWave][D], s_mx[kThreads / kWave][D];
-        const int64_t v = first + blockIdx.x;
-        if (blockIdx.x >= count)
-            return;
-        uint64_t kmax;
-        uint32_t mn[D], mx[D];
-        node_scan<D>(A, cap, seg_start(sh, v, l), sub_size(sh, v, l), threadIdx.x, kThreads, kmax, mn, mx);
-        wave_reduce<D>(kmax, mn, mx);
-        const int w = threadIdx.x / kWave;
-        if (__lane_id() == 0) {
-            s_k[w] = kmax;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                s_mn[w][k] = mn[k];
-                s_mx[w][k] = mx[k];
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int q = 1; q < kThreads / kWave; ++q) {
-                kmax = s_k[q] > kmax ? s_k[q] : kmax;
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    mn[k] = s_mn[q][k] < mn[k] ? s_mn[q][k] : mn[k];
-                    mx[k] = s_mx[q][k] > mx[k] ? s_mx[q][k] : mx[k];
-                }
-            }
-            store_node<D>(T, v, kmax, mn, mx);
-        }
-    } else if constexpr (MODE == 1) {
+    if constexpr (MODE == 1) {
         const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
         if (i >= count)
             return;
@@ -190,8 +143,11 @@ __global__ __launch_bounds__(kThreads) void k_pst_reduce(Level A, int64_t cap, S
         uint64_t kmax;
         uint32_t mn[D], mx[D];
         node_scan<D>(A, cap, seg_start(sh, v, l), sub_size(sh, v, l), __lane_id(), kWave, kmax, mn, mx);
-        wave_reduce<D>(kmax, mn, mx);
-        if (__lane_id() == 0)
+        kmax = group_max_u64<6>(kmax);
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            group_min_max<6>(mn[k], mx[k]);
+        if (__lane_id() == kWave - 1)
             store_node<D>(T, v, kmax, mn, mx);
     } else {
         const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -203,6 +159,98 @@ __global__ __launch_bounds__(kThreads) void k_pst_reduce(Level A, int64_t cap, S
         node_scan<D>(A, cap, seg_start(sh, v, l), sub_size(sh, v, l), 0, 1, kmax, mn, mx);
         store_node<D>(T, v, kmax, mn, mx);
     }
+}
+
+// Step (1) for depths whose subtrees are large: each wavefront reduces one
+// chunk of kChunk consecutive points of one node (a node's points are
+// consecutive in the level's array, so chunks never straddle two), with the
+// cross-lane steps done by DPP moves, into one partial per chunk; then one
+// wavefront per node combines the node's partials.  cpn chunks per node
+// (enough for the largest subtree of the depth; chunks past a smaller
+// subtree's end are empty).
+constexpr int kChunk = 1024;
+
+template <int D>
+struct Partial {
+    uint64_t key;
+    uint32_t mn[D], mx[D];
+};
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_pst_part(Level A, int64_t cap, Shape sh, int l, int64_t cpn,
+                                                       Partial<D> *__restrict__ part) {
+    const int64_t first = 1ll << l;
+    const int64_t count = (l == sh.h ? sh.n + 1 : 2 * first) - first;
+    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;  // wave-uniform
+    if (g >= count * cpn)
+        return;
+    const int64_t v = first + g / cpn;
+    const int64_t s0 = seg_start(sh, v, l), m = sub_size(sh, v, l);
+    const int64_t b = (g % cpn) * kChunk;
+    const int64_t e = b + kChunk < m ? b + kChunk : m;
+    uint64_t kmax = 0;
+    uint32_t mn[D], mx[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        mn[k] = 0xFFFFFFFFu;
+        mx[k] = 0u;
+    }
+    for (int64_t p = s0 + b + __lane_id(); p < s0 + e; p += kWave) {
+        const uint64_t kk = A.key[p];
+        kmax = kk > kmax ? kk : kmax;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const uint32_t x = A.x[(int64_t)k * cap + p];
+            mn[k] = x < mn[k] ? x : mn[k];
+            mx[k] = x > mx[k] ? x : mx[k];
+        }
+    }
+    kmax = group_max_u64<6>(kmax);
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        group_min_max<6>(mn[k], mx[k]);
+    if (__lane_id() == kWave - 1) {
+        Partial<D> r;
+        r.key = kmax;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            r.mn[k] = mn[k];
+            r.mx[k] = mx[k];
+        }
+        part[g] = r;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_pst_combine(Shape sh, int l, int64_t cpn,
+                                                          const Partial<D> *__restrict__ part, Tree T) {
+    const int64_t first = 1ll << l;
+    const int64_t count = (l == sh.h ? sh.n + 1 : 2 * first) - first;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;  // wave-uniform
+    if (i >= count)
+        return;
+    uint64_t kmax = 0;
+    uint32_t mn[D], mx[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        mn[k] = 0xFFFFFFFFu;
+        mx[k] = 0u;
+    }
+    for (int64_t c = __lane_id(); c < cpn; c += kWave) {
+        const Partial<D> &r = part[i * cpn + c];
+        kmax = r.key > kmax ? r.key : kmax;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            mn[k] = r.mn[k] < mn[k] ? r.mn[k] : mn[k];
+            mx[k] = r.mx[k] > mx[k] ? r.mx[k] : mx[k];
+        }
+    }
+    kmax = group_max_u64<6>(kmax);
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        group_min_max<6>(mn[k], mx[k]);
+    if (__lane_id() == kWave - 1)
+        store_node<D>(T, first + i, kmax, mn, mx);
 }
 
 // Longest side of node v's box (the lowest axis on a tie).
@@ -398,6 +446,18 @@ dpc_status pst_typed(const Job &J, Workspace &ws) {
     DPC_TRY(ws.alloc(&kb, (size_t)cap));
     DPC_TRY(ws.alloc(&va, (size_t)cap));
     DPC_TRY(ws.alloc(&vb, (size_t)cap));
+    // chunk partials of the depths with large subtrees: nodes x chunks per
+    // node at each such depth (the launches below index exactly that many)
+    int64_t part_entries = 1;
+    for (int l = 0; l < sh.h; ++l) {
+        const int64_t seg = sub_size(sh, 1ll << l, l);
+        if (seg >= 4096) {
+            const int64_t need = (1ll << l) * ((seg + kChunk - 1) / kChunk);
+            part_entries = need > part_entries ? need : part_entries;
+        }
+    }
+    Partial<D> *part;
+    DPC_TRY(ws.alloc(&part, (size_t)part_entries));
     Corner lo{};
     for (int k = 0; k < kMaxDim; ++k)
         lo.v[k] = J.lo[k];
@@ -407,9 +467,13 @@ dpc_status pst_typed(const Job &J, Workspace &ws) {
         const int64_t m = n - ((1ll << l) - 1);
         const int64_t nodes = 1ll << l;
         const int64_t seg = sub_size(sh, 1ll << l, l);  // the largest subtree of this depth
-        if (seg >= 4096)
-            launch((k_pst_reduce<D, 0>), dim3((unsigned)nodes), dim3(kThreads), 0, s, A, cap, sh, l, T);
-        else if (seg >= 64)
+        if (seg >= 4096) {
+            const int64_t cpn = (seg + kChunk - 1) / kChunk;
+            launch((k_pst_part<D>), dim3(blocks_for(nodes * cpn * kWave, kThreads)), dim3(kThreads), 0, s, A, cap,
+                   sh, l, cpn, part);
+            launch((k_pst_combine<D>), dim3(blocks_for(nodes * kWave, kThreads)), dim3(kThreads), 0, s, sh, l, cpn,
+                   (const Partial<D> *)part, T);
+        } else if (seg >= 64)
             launch((k_pst_reduce<D, 1>), dim3(blocks_for(nodes * kWave, kThreads)), dim3(kThreads), 0, s, A, cap,
                    sh, l, T);
         else

@@ -11,7 +11,9 @@
 // The walk goes bottom-up: first the home node, then the sibling subtree of
 // each ancestor of the home node from the deepest up, which together hold
 // every point once; near candidates are met first, so the distance bounds
-// are tight by the time the large subtrees near the root are tested.  Inside
+// are tight by the time the large subtrees near the root are tested, and the
+// walk stops early once every lane's best is nearer than the boundary of the
+// finished ancestor's box.  Inside
 // a subtree the nearer child (for the first lane that still needs the node)
 // is visited first.  A leaf that few lanes need is searched cooperatively
 // (leaf_coop), one that many need by each of those lanes in turn.
@@ -352,6 +354,25 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
         // this subtree is done: the next one is the sibling of the next ancestor
         if (a <= 1)
             break;
+        {
+            // Every point not yet searched lies outside subtree a, beyond one
+            // of the split planes that bound it, and a's box lies on this
+            // side of each of them: such a point is at least the query's gap
+            // to the box's boundary away.  A lane whose best is below the
+            // square of that gap is settled (an equal distance could still
+            // meet a smaller index), and when every lane is, the walk ends.
+            const C *ab = box + (size_t)a * 2 * D;
+            C g = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const C lo_gap = x[k] - ab[2 * k], hi_gap = ab[2 * k + 1] - x[k];
+                const C m = lo_gap < hi_gap ? lo_gap : hi_gap;
+                g = k == 0 ? m : (m < g ? m : g);
+            }
+            const bool settled = !active || (best_low != 0 && best < g * g);
+            if (__builtin_amdgcn_ballot_w64(!settled) == 0)
+                break;
+        }
         v = a ^ 1u;
         depth = da;
         u = 1;

@@ -13,10 +13,11 @@
 // every point once; near candidates are met first, so the distance bounds
 // are tight by the time the large subtrees near the root are tested, and the
 // walk stops early once every lane's best is nearer than the boundary of the
-// finished ancestor's box.  Inside
-// a subtree the nearer child (for the first lane that still needs the node)
-// is visited first.  A leaf that few lanes need is searched cooperatively
-// (leaf_coop), one that many need by each of those lanes in turn.
+// finished ancestor's box.  Inside a subtree the child on the side of the
+// wave's first query is visited first (measured better than the side of the
+// first lane that still needs the node, or of the home node's centre).  A
+// leaf that few lanes need is searched cooperatively (leaf_coop), one that
+// many need by each of those lanes in turn.
 #include "traverse.hpp"
 
 #include <limits>

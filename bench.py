@@ -227,6 +227,7 @@ def batched(torch, dpc, datagen, steps: int, trace_only: bool = False) -> dict:
         k = max((i for i, x in enumerate(insts) if x.d == d), key=lambda i: insts[i].n)
         r = dpc.autotune(*probs[k])
         tuned[str(d)] = {"instance_n": insts[k].n, "ms_leaf16": r["ms"][16], "ms_leaf32": r["ms"][32],
+                         "ms_leaf64": r["ms"][64],
                          "leaf_points": r["chosen"]}
     B = dpc.Batch(probs)
     B.run()  # warm-up (pool growth, code loading)

@@ -416,21 +416,23 @@ DPC_API int dpc_server_destroy(dpc_server *server);
 
 /*
  * Tuning (never changes any output).  Points per k-d tree leaf, per
- * dimension: 16 or 32.  Smaller leaves prune more point tests and visit
- * more nodes.  The setting is process-wide and read when a call builds its
- * index, so it applies to later calls on any thread and stream.
+ * dimension: 16, 32 or 64 (the default).  Smaller leaves prune more point
+ * tests and visit more nodes.  The setting is process-wide and read when a
+ * call builds its index, so it applies to later calls on any thread and
+ * stream.
  * dpc_set_leaf_size: DPC_ERR_INVALID_ARG for d outside [1, 8] or another size.
  * dpc_leaf_size: the current size for d (0 for an invalid d).
  */
+#define DPC_LEAF_SIZES 3
 DPC_API int dpc_set_leaf_size(int32_t d, int32_t leaf_points);
 DPC_API int32_t dpc_leaf_size(int32_t d);
 
 /*
  * Autotuner: runs the whole method on the given instance with each leaf size
  * (one warm-up and two timed runs each, HIP events on `stream`), keeps the
- * faster size for dimension d (as dpc_set_leaf_size) and returns the two
- * times in ms_out[0] (16 points) and ms_out[1] (32 points) and the choice in
- * *chosen (either may be NULL).  Arguments as for dpc_run; the outputs go to
+ * fastest size for dimension d (as dpc_set_leaf_size) and returns the
+ * DPC_LEAF_SIZES times in ms_out[0] (16 points), ms_out[1] (32 points) and
+ * ms_out[2] (64 points) and the choice in *chosen (either may be NULL).  Arguments as for dpc_run; the outputs go to
  * workspace and are discarded.  Synchronises the stream.  On failure the
  * previous setting is kept.
  */

@@ -13,6 +13,7 @@ from ._binding import (  # noqa: F401
     Instance,
     EXPORTED,
     INF,
+    LEAF_SIZES,
     LIB_PATH,
     Plan,
     SKIP_NOISE_DEPENDENTS,

@@ -564,8 +564,11 @@ class BatchPlan(Plan):
         return self._b.statuses()
 
 
+LEAF_SIZES = (16, 32, 64)
+
+
 def set_leaf_size(d: int, leaf_points: int) -> None:
-    """Points per k-d tree leaf (16 or 32) for dimension d; never changes outputs."""
+    """Points per k-d tree leaf (16, 32 or 64) for dimension d; never changes outputs."""
     st = load().dpc_set_leaf_size(int(d), int(leaf_points))
     if st != OK:
         raise DPCError(st, "dpc_set_leaf_size")
@@ -576,16 +579,16 @@ def leaf_size(d: int) -> int:
 
 
 def autotune(points, d_cut: float, rho_min: int, delta_min: float, stream=None) -> dict:
-    """Times both leaf sizes on this instance and keeps the faster for its
-    dimension; returns {"ms": {16: t16, 32: t32}, "chosen": size}."""
+    """Times every leaf size on this instance and keeps the fastest for its
+    dimension; returns {"ms": {16: t16, 32: t32, 64: t64}, "chosen": size}."""
     n, d = _check_points(points)
-    ms = (ctypes.c_double * 2)()
+    ms = (ctypes.c_double * len(LEAF_SIZES))()
     ch = ctypes.c_int32()
     st = load().dpc_autotune(_ptr(points), n, d, float(d_cut), int(rho_min), float(delta_min), _stream(stream), ms,
                              ctypes.byref(ch))
     if st != OK:
         raise DPCError(st, "dpc_autotune")
-    return {"ms": {16: ms[0], 32: ms[1]}, "chosen": ch.value}
+    return {"ms": {size: ms[c] for c, size in enumerate(LEAF_SIZES)}, "chosen": ch.value}
 
 
 def set_dependent_backend(d: int, backend: str) -> None:

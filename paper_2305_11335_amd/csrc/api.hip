@@ -751,9 +751,9 @@ uint64_t dpc_workspace_bytes(int64_t n, int32_t d) {
 }
 
 int dpc_set_leaf_size(int32_t d, int32_t leaf_points) {
-    if (d < 1 || d > kMaxDim || (leaf_points != 16 && leaf_points != 32))
+    if (d < 1 || d > kMaxDim || (leaf_points != 16 && leaf_points != 32 && leaf_points != 64))
         return DPC_ERR_INVALID_ARG;
-    set_leaf_log2(d, leaf_points == 16 ? 4 : 5);
+    set_leaf_log2(d, leaf_points == 16 ? 4 : (leaf_points == 32 ? 5 : 6));
     return DPC_OK;
 }
 
@@ -768,9 +768,9 @@ int dpc_autotune(const int32_t *points, int64_t n, int32_t d, double d_cut, int3
     if (bad_shape(n, d) || n == 0 || points == nullptr)
         return DPC_ERR_INVALID_ARG;
     const int before = leaf_log2(d);
-    float best_ms[2] = {0.0f, 0.0f};
+    float best_ms[DPC_LEAF_SIZES] = {};
     dpc_status st = DPC_OK;
-    for (int c = 0; c < 2 && st == DPC_OK; ++c) {
+    for (int c = 0; c < DPC_LEAF_SIZES && st == DPC_OK; ++c) {
         set_leaf_log2(d, kMinLeafLog2 + c);
         st = time_choice(points, n, d, d_cut, rho_min, delta_min, DPC_BACKEND_PRIORITY_TREE, stream, &best_ms[c]);
     }
@@ -778,11 +778,14 @@ int dpc_autotune(const int32_t *points, int64_t n, int32_t d, double d_cut, int3
         set_leaf_log2(d, before);
         return st;
     }
-    const int pick = best_ms[0] < best_ms[1] ? kMinLeafLog2 : kMaxLeafLog2;
+    int pick = 0;
+    for (int c = 1; c < DPC_LEAF_SIZES; ++c)
+        pick = best_ms[c] < best_ms[pick] ? c : pick;
+    pick += kMinLeafLog2;
     set_leaf_log2(d, pick);
     if (ms_out) {
-        ms_out[0] = best_ms[0];
-        ms_out[1] = best_ms[1];
+        for (int c = 0; c < DPC_LEAF_SIZES; ++c)
+            ms_out[c] = best_ms[c];
     }
     if (chosen)
         *chosen = 1 << pick;

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
     // one staged leaf per wave: D 8-byte coordinates or W packed words per point
     // (also the query slots of the cooperative count: at most kDenCoopMax)
     __shared__ uint64_t s_leaf[kThreads / kWave]
-                              [D >= 3 ? (kMaxLeaf > kDenCoopMax ? kMaxLeaf : kDenCoopMax) * D
+                              [D >= 3 ? ((1 << LSH) > kDenCoopMax ? (1 << LSH) : kDenCoopMax) * D
                                       : (den_coop_max<D>() > 0 ? den_coop_max<D>() * D : 1)];
     uint64_t n_pairs = 0, n_nodes = 0, n_contained = 0, w_nodes = 0, w_points = 0;
     const int lane = __lane_id();
@@ -388,10 +388,16 @@ __global__ __launch_bounds__(kThreads) void k_density(const Inst *__restrict__ i
             const uint32_t *pk = nw.pack + start * W;
             if constexpr (kStage) {
                 uint32_t *sp = reinterpret_cast<uint32_t *>(s_leaf[w]);
-                if (lane < (int)count * W)
-                    sp[lane] = pk[lane];
-                if (W > 2 && lane + kWave < (int)count * W)
-                    sp[lane + kWave] = pk[lane + kWave];
+                if constexpr (lsh <= 5) {
+                    // at most 32 points of at most 4 words: two loads per lane
+                    if (lane < (int)count * W)
+                        sp[lane] = pk[lane];
+                    if (W > 2 && lane + kWave < (int)count * W)
+                        sp[lane + kWave] = pk[lane + kWave];
+                } else {
+                    for (int j = lane; j < (int)count * W; j += kWave)
+                        sp[j] = pk[j];
+                }
                 pk = sp;
             }
             if ((int32_t)nw.ext[c] <= nw.limit) {
@@ -584,8 +590,8 @@ dpc_status launch_leaf(const Index &ix, int32_t *srho, int64_t *counters, hipStr
 }  // namespace
 
 dpc_status launch_density(const Index &ix, int32_t *srho, int64_t *counters, hipStream_t s) {
-    return ix.lsh == kMinLeafLog2 ? launch_leaf<kMinLeafLog2>(ix, srho, counters, s)
-                                  : launch_leaf<kMaxLeafLog2>(ix, srho, counters, s);
+    return ix.lsh == 4 ? launch_leaf<4>(ix, srho, counters, s)
+                       : (ix.lsh == 5 ? launch_leaf<5>(ix, srho, counters, s) : launch_leaf<6>(ix, srho, counters, s));
 }
 
 }  // namespace dpc

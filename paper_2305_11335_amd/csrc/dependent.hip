@@ -91,18 +91,21 @@ __device__ inline void lex_min_step(C &s, uint32_t &l) {
 
 // Lexicographic minimum of (D^2, index) over groups of 2^G lanes (a larger
 // low key word is a smaller index), by DPP lane moves: within quads, the
-// mirrored halves of 8- and 16-lane rows, then (G = 5) row 1 from row 0's and
-// row 3 from row 2's last lane.  The result is in every lane of a 16-lane
-// group and in the last lane of a 32-lane one.
+// mirrored halves of 8- and 16-lane rows, then (G >= 5) row 1 from row 0's
+// and row 3 from row 2's last lane, and (G = 6) rows 2 and 3 from lane 31.
+// The result is in every lane of a 16-lane group and in the last lane of a
+// 32- or 64-lane one.
 template <int G, typename C>
 __device__ inline void group_lex_min(C &s, uint32_t &l) {
-    static_assert(G == 4 || G == 5, "groups of 16 or 32 lanes");
+    static_assert(G >= 4 && G <= 6, "groups of 16, 32 or 64 lanes");
     lex_min_step<0xB1, 0xF>(s, l);   // quad_perm [1,0,3,2]
     lex_min_step<0x4E, 0xF>(s, l);   // quad_perm [2,3,0,1]
     lex_min_step<0x141, 0xF>(s, l);  // row_half_mirror
     lex_min_step<0x140, 0xF>(s, l);  // row_mirror
-    if constexpr (G == 5)
+    if constexpr (G >= 5)
         lex_min_step<0x142, 0xA>(s, l);  // row_bcast:15 into rows 1 and 3
+    if constexpr (G >= 6)
+        lex_min_step<0x143, 0xC>(s, l);  // row_bcast:31 into rows 2 and 3
 }
 
 // A leaf that few lanes of the wave want.  Looping each of those lanes over
@@ -163,7 +166,8 @@ __device__ inline void leaf_coop(const C *__restrict__ coords, const uint64_t *_
             C hs = hit ? s : std::numeric_limits<C>::max();
             uint32_t hl = hit ? (uint32_t)pk : 0u;
             group_lex_min<LSH, C>(hs, hl);
-            const bool any = ((hm >> (kL * grp)) & ((1ull << kL) - 1ull)) != 0;
+            const uint64_t gm = kL == kWave ? ~0ull : ((1ull << (kL % kWave)) - 1ull) << (kL * grp);
+            const bool any = (hm & gm) != 0;
             if (pl == kL - 1 && live && any) {
                 const uint32_t ql = sql[rr];
                 if ((hs < qb) | ((hs == qb) & (hl > ql))) {
@@ -197,8 +201,8 @@ __global__ __launch_bounds__(kThreads) void k_dependent(const C *__restrict__ co
                                                         int64_t *__restrict__ delta2_out, int64_t *counters,
                                                         const Inst *__restrict__ inst,
                                                         const uint32_t *__restrict__ tile_inst) {
-    __shared__ C s_pts[kThreads / kWave][kMaxLeaf * D];
-    __shared__ uint64_t s_key[kThreads / kWave][kMaxLeaf];
+    __shared__ C s_pts[kThreads / kWave][(1 << LSH) * D];
+    __shared__ uint64_t s_key[kThreads / kWave][1 << LSH];
     // query slots of the cooperative leaf path
     constexpr int kCoopMax = coop_max<D>();
     __shared__ C s_qx[kThreads / kWave][kCoopMax * D];
@@ -435,11 +439,14 @@ dpc_status launch_typed(const Index &ix, int64_t *counters, hipStream_t s) {
 
 template <typename C, bool STATS>
 dpc_status launch_arith(const Index &ix, int64_t *counters, hipStream_t s) {
-    if (ix.lsh == kMinLeafLog2)
-        return ix.count == 1 ? launch_typed<C, STATS, false, kMinLeafLog2>(ix, counters, s)
-                             : launch_typed<C, STATS, true, kMinLeafLog2>(ix, counters, s);
-    return ix.count == 1 ? launch_typed<C, STATS, false, kMaxLeafLog2>(ix, counters, s)
-                         : launch_typed<C, STATS, true, kMaxLeafLog2>(ix, counters, s);
+    if (ix.lsh == 4)
+        return ix.count == 1 ? launch_typed<C, STATS, false, 4>(ix, counters, s)
+                             : launch_typed<C, STATS, true, 4>(ix, counters, s);
+    if (ix.lsh == 5)
+        return ix.count == 1 ? launch_typed<C, STATS, false, 5>(ix, counters, s)
+                             : launch_typed<C, STATS, true, 5>(ix, counters, s);
+    return ix.count == 1 ? launch_typed<C, STATS, false, 6>(ix, counters, s)
+                         : launch_typed<C, STATS, true, 6>(ix, counters, s);
 }
 
 }  // namespace

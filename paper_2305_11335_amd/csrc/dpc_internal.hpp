@@ -32,9 +32,9 @@ namespace dpc {
 
 constexpr int kWave = 64;
 constexpr int kMaxDim = 8;
-constexpr int kMaxLeaf = 32;   // most points per tree leaf (a group's leaves hold 16 or 32)
+constexpr int kMaxLeaf = 64;   // most points per tree leaf (a group's leaves hold 16, 32 or 64)
 constexpr int kMinLeafLog2 = 4;
-constexpr int kMaxLeafLog2 = 5;
+constexpr int kMaxLeafLog2 = 6;
 constexpr int kTile = 2048;    // positions per tile (the unit of the top-level build passes)
 
 // A DPP lane move (dpp_ctrl CTRL) within the rows selected by ROWS: each

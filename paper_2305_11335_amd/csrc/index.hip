@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_keys_leaf(const Inst *__restrict__
     }
     // the leaf's maximum, by DPP lane moves, lands in its last lane
     const int lsh = I.lsh;
-    key = lsh == kMaxLeafLog2 ? group_max_u64<kMaxLeafLog2>(key) : group_max_u64<kMinLeafLog2>(key);
+    key = lsh == 6 ? group_max_u64<6>(key) : (lsh == 5 ? group_max_u64<5>(key) : group_max_u64<4>(key));
     const int64_t first = i - ((1 << lsh) - 1);  // the leaf's first position
     if ((i & ((1 << lsh) - 1)) == (1 << lsh) - 1 && first < I.n)
         maxkey[I.N + (1ll << I.height) + (i >> lsh)] = key;
@@ -430,7 +430,7 @@ void density_params(Inst &I, int64_t T, int d) {
 // Any choice gives the same outputs.
 namespace {
 #ifndef DPC_DEFAULT_LSH
-#define DPC_DEFAULT_LSH 5
+#define DPC_DEFAULT_LSH 6
 #endif
 std::atomic<int> g_leaf_log2[kMaxDim + 1] = {DPC_DEFAULT_LSH, DPC_DEFAULT_LSH, DPC_DEFAULT_LSH,
                                              DPC_DEFAULT_LSH, DPC_DEFAULT_LSH, DPC_DEFAULT_LSH,

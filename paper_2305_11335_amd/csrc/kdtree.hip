@@ -1340,12 +1340,16 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
         }
     }
     const unsigned bgrid = single ? (unsigned)(1ll << ix.host[0].jb) : (unsigned)subs.size();
-    if (ix.lsh == kMinLeafLog2)
-        launch((k_bottom<C, D, kMinLeafLog2>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst,
+    if (ix.lsh == 4)
+        launch((k_bottom<C, D, 4>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst,
+                           single ? nullptr : d_subs, XA, XB, IA, IB, np, box, ix.rbox, coords, ix.sidx, ix.leaf_org,
+                           ix.leaf_ext, ix.leaf_pack, ix.split);
+    else if (ix.lsh == 5)
+        launch((k_bottom<C, D, 5>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst,
                            single ? nullptr : d_subs, XA, XB, IA, IB, np, box, ix.rbox, coords, ix.sidx, ix.leaf_org,
                            ix.leaf_ext, ix.leaf_pack, ix.split);
     else
-        launch((k_bottom<C, D, kMaxLeafLog2>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst,
+        launch((k_bottom<C, D, 6>), dim3(bgrid), dim3(kThreads), 0, s, ix.inst,
                            single ? nullptr : d_subs, XA, XB, IA, IB, np, box, ix.rbox, coords, ix.sidx, ix.leaf_org,
                            ix.leaf_ext, ix.leaf_pack, ix.split);
     DPC_HIP(hipGetLastError());

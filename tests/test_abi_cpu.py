@@ -222,14 +222,14 @@ def test_sweep_argument_errors():
 
 def test_leaf_size_setting_is_host_only():
     for d in range(1, 9):
-        assert dpc.leaf_size(d) in (16, 32)
+        assert dpc.leaf_size(d) in dpc.LEAF_SIZES
     assert dpc.load().dpc_leaf_size(0) == 0 and dpc.load().dpc_leaf_size(9) == 0
     before = dpc.leaf_size(5)
-    for size in (16, 32):
+    for size in (16, 32, 64):
         dpc.set_leaf_size(5, size)
         assert dpc.leaf_size(5) == size
     dpc.set_leaf_size(5, before)
-    for d, size in ((0, 16), (9, 32), (3, 8), (3, 64), (2, 31)):
+    for d, size in ((0, 16), (9, 32), (3, 8), (3, 128), (2, 31), (2, 48)):
         with pytest.raises(dpc.DPCError):
             dpc.set_leaf_size(d, size)
     lib = dpc.load()

@@ -1,7 +1,7 @@
-"""GPU parity under both k-d tree leaf sizes (16 and 32 points).
+"""GPU parity under every k-d tree leaf size (16, 32 and 64 points).
 
-The leaf size is a tuning choice: every output must be the same with either,
-equal to the oracle on small inputs and equal between the two sizes on the
+The leaf size is a tuning choice: every output must be the same with any,
+equal to the oracle on small inputs and equal between the sizes on the
 full-size workloads.  The autotuner must pick one of them and leave the
 outputs unchanged.
 """
@@ -42,7 +42,7 @@ def same(got, want, what):
             raise AssertionError(f"{what}: {name} differs at {int((g != w).sum())} places, first {i}: {g[i]} vs {w[i]}")
 
 
-@pytest.fixture(params=[16, 32], ids=["leaf16", "leaf32"])
+@pytest.fixture(params=[16, 32, 64], ids=["leaf16", "leaf32", "leaf64"])
 def leaf(request):
     before = {d: dpc.leaf_size(d) for d in range(1, 9)}
     for d in range(1, 9):
@@ -69,7 +69,7 @@ def test_random_tiny(leaf):
 
 @pytest.mark.parametrize("d", [2, 3, 5, 8])
 def test_ragged_sizes(leaf, d):
-    for n in (1, 15, 16, 17, 31, 33, 63, 65, 127, 513, 1023, 1025, 2047, 2049, 4097):
+    for n in (1, 15, 16, 17, 31, 33, 63, 64, 65, 127, 129, 513, 1023, 1025, 2047, 2049, 4097):
         pts = datagen.clustered_small(n * 3 + d, n, d, span=1 << 16, k=3, sd_frac=0.01)
         d_cut = {2: 600.0, 3: 2000.0, 5: 6000.0, 8: 12000.0}[d]
         got = host(dpc.run(dev(pts), d_cut, 3, 4 * d_cut))
@@ -93,19 +93,20 @@ def test_batch(leaf):
 
 
 @pytest.mark.parametrize("name", ["varden2d_10m", "mix3d_10m"])
-def test_full_size_both_leaf_sizes_agree(name):
+def test_full_size_leaf_sizes_agree(name):
     x = datagen.make(name)
     P = dev(x.points)
     before = dpc.leaf_size(x.d)
     try:
         res = {}
-        for size in (16, 32):
+        for size in (16, 32, 64):
             dpc.set_leaf_size(x.d, size)
             res[size] = host(dpc.run(P, x.d_cut, x.rho_min, x.delta_min))
             say(name, "leaf", size, "done")
     finally:
         dpc.set_leaf_size(x.d, before)
-    same(res[16], res[32], f"{name}: leaf 16 against leaf 32")
+    same(res[16], res[64], f"{name}: leaf 16 against leaf 64")
+    same(res[32], res[64], f"{name}: leaf 32 against leaf 64")
 
 
 def test_autotune_keeps_outputs():
@@ -116,9 +117,9 @@ def test_autotune_keeps_outputs():
         ref = host(dpc.run(P, x.d_cut, x.rho_min, x.delta_min))
         r = dpc.autotune(P, x.d_cut, x.rho_min, x.delta_min)
         say("autotune", r)
-        assert r["chosen"] in (16, 32) and dpc.leaf_size(3) == r["chosen"]
-        assert r["ms"][16] > 0 and r["ms"][32] > 0
-        assert r["chosen"] == (16 if r["ms"][16] < r["ms"][32] else 32)
+        assert r["chosen"] in dpc.LEAF_SIZES and dpc.leaf_size(3) == r["chosen"]
+        assert all(r["ms"][size] > 0 for size in dpc.LEAF_SIZES)
+        assert r["chosen"] == min(dpc.LEAF_SIZES, key=lambda size: r["ms"][size])
         same(host(dpc.run(P, x.d_cut, x.rho_min, x.delta_min)), ref, "after autotune")
     finally:
         dpc.set_leaf_size(3, before)

@@ -1,7 +1,8 @@
 // Density (Section 3, Definition 1): rho_i = #{ j : D^2(i, j) <= T }.
 //
-// Each wavefront takes 64 consecutive sorted points (the two leaves below one
-// node, its "home" node) and walks the tree.  For every node a lane classifies
+// Each wavefront takes 64 consecutive sorted points (one leaf of 64 points,
+// or the two or four leaves below one node: its "home" node) and walks the
+// tree.  For every node a lane classifies
 // the node's box against its own ball:
 //   outside  (nearest corner beyond the radius)   -> nothing to count;
 //   inside   (farthest corner within the radius)  -> add the node's point

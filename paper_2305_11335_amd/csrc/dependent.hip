@@ -7,7 +7,8 @@
 // like any node whose box is farther than the best distance found so far.
 // A node at exactly the best distance is still visited, since it may hold an
 // equally near point of smaller index.  Each wavefront walks the tree with 64
-// consecutive sorted queries, the points of its "home" node (two leaves).
+// consecutive sorted queries, the points of its "home" node (one, two or
+// four leaves by leaf size).
 // The walk goes bottom-up: first the home node, then the sibling subtree of
 // each ancestor of the home node from the deepest up, which together hold
 // every point once; near candidates are met first, so the distance bounds

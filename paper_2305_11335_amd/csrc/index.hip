@@ -425,9 +425,9 @@ void density_params(Inst &I, int64_t T, int d) {
 }
 
 // Leaf size per dimension (log2).  Smaller leaves prune more point tests but
-// visit more nodes; on the stand-in workloads 32 points were faster in 2-D,
-// 3-D and 8-D, so it is the default (dpc_autotune measures an instance).
-// Any choice gives the same outputs.
+// visit more nodes; on the stand-in workloads 64 points were the fastest in
+// 2-D, 3-D and 8-D, so it is the default (dpc_autotune measures an
+// instance).  Any choice gives the same outputs.
 namespace {
 #ifndef DPC_DEFAULT_LSH
 #define DPC_DEFAULT_LSH 6

@@ -105,6 +105,18 @@ __device__ inline uint64_t group_max_u64(uint64_t v) {
 // 20 bits), 8 below (small histograms for many nodes).
 __host__ __device__ inline int top_level_bits(int j) { return j <= 8 ? 11 : (j <= 12 ? 10 : 8); }
 
+// Top levels whose nodes hold at most 2^kOwnLog2 points are split by one
+// workgroup per node, which keeps its histograms in LDS; the shared
+// histograms exist for the levels above only.
+constexpr int kOwnLog2 = 15;
+
+// First top level of an instance split one workgroup per node (at most jb,
+// its first level built in LDS).
+__host__ __device__ inline int top_owned_from(int height, int lsh, int jb) {
+    const int f = height + lsh - kOwnLog2;
+    return f < 0 ? 0 : (f > jb ? jb : f);
+}
+
 // Coordinates and squared distances are exact in double when every squared
 // distance stays below 2^53 (the "f64" path); otherwise 64-bit integers.
 enum class Arith { F64, I64 };

@@ -513,8 +513,9 @@ dpc_status build_group(const std::vector<Job> &jobs, int d, Arith arith, int lsh
         P += padded(J.n);
         N += 2ll << I.height;
         L += 1ll << I.height;
+        // shared histograms for the levels above those split one workgroup per node
         int64_t hw = 0;
-        for (int l = 0; l < I.jb; ++l) {
+        for (int l = 0; l < top_owned_from(I.height, lsh, I.jb); ++l) {
             const int bits = top_level_bits(l);
             hw += (int64_t)((I.wbits + bits - 1) / bits) * (1ll << l) * (1ll << bits);
         }

@@ -29,6 +29,7 @@
 // the group; each kernel finds its instance from its tile.
 #include "dpc_internal.hpp"
 
+#include <algorithm>
 #include <limits>
 
 namespace dpc {
@@ -176,11 +177,11 @@ struct TopTile {
 };
 
 // False when the tile has no work at level j (padding, or an instance whose
-// level j is built in LDS).
+// level j is built in LDS or split one workgroup per node).
 __device__ inline bool top_tile(const Inst *__restrict__ inst, const uint32_t *__restrict__ tile_inst, int64_t tile,
                                 int j, TopTile &tt) {
     const Inst &I = inst_of_tile(inst, tile_inst, tile);
-    if (j >= I.jb)
+    if (j >= top_owned_from(I.height, I.lsh, I.jb))
         return false;
     const int64_t first = I.P / kTile;
     tt.e0 = (tile - first) * kTile;
@@ -200,7 +201,7 @@ __device__ inline bool top_node(const Inst *__restrict__ inst, const uint2 *__re
                                 TopTile &tt) {
     const uint2 e = node_tab ? node_tab[blockIdx.x] : make_uint2(0u, blockIdx.x);
     const Inst &I = inst[e.x];
-    if (j >= I.jb)
+    if (j >= top_owned_from(I.height, I.lsh, I.jb))
         return false;
     const int64_t S = 1ll << (I.height - j + I.lsh);
     tt.t = e.y;
@@ -713,6 +714,227 @@ __global__ __launch_bounds__(kThreads) void k_box_reduce(const Inst *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// top levels with small nodes: one workgroup per node
+
+// Splits every node of level j that holds at most 2^kOwnLog2 points with one
+// workgroup of NT threads: the node's median along its split axis by radix
+// select over an LDS histogram (11-bit digits, each pass reading the node's
+// axis values again), then the same stable partition as the shared passes
+// (points below the median, then the first need_eq points equal to it, go
+// left) in runs of NT * kItems points in array order, with the children's
+// boxes reduced on the way.  It writes the same records as those passes.
+template <typename C, int D, int NT>
+__global__ __launch_bounds__(NT) void k_node_split(const Inst *__restrict__ inst, const uint2 *__restrict__ node_tab,
+                                                   TopArrays A, const uint32_t *__restrict__ Iin_all,
+                                                   uint32_t *__restrict__ Xout_all, uint32_t *__restrict__ Iout_all,
+                                                   int j, C *__restrict__ tree_box, uint32_t *__restrict__ rel_box,
+                                                   uint64_t *__restrict__ split_hint) {
+    constexpr int kB = 11;
+    constexpr int kBins = 1 << kB;
+    constexpr int kPer = kBins / NT;  // bins per thread in the pick
+    constexpr int NW = NT / kWave;
+    constexpr int kRun = NT * kItems;  // positions per run
+    static_assert(kPer >= 1 && kBins % NT == 0, "whole bins per thread");
+    __shared__ uint32_t s_h[kBins];
+    __shared__ uint32_t s_w[2][2][NW];  // [run parity][below, equal][wave]
+    __shared__ uint32_t s_scan[NW];
+    __shared__ uint32_t s_pick[2];
+    __shared__ uint32_t s_box[NW][4 * D];
+
+    const uint2 job = node_tab ? node_tab[blockIdx.x] : make_uint2(0u, blockIdx.x);
+    const Inst &I = inst[job.x];
+    if (j < top_owned_from(I.height, I.lsh, I.jb) || j >= I.jb)
+        return;
+    const int64_t n = I.n;
+    const int64_t S = 1ll << (I.height - j + I.lsh);
+    const int64_t t = job.y;
+    if (t * S >= n)
+        return;
+    const NodeGeom g = node_geom(t, S, n);
+    const int64_t end = g.start + g.count;
+    const uint32_t *nb = A.nboxes + I.B + ((1ll << j) + t) * 2 * D;
+    const NodeSelect ns = node_select<D, kB>(nb);
+    const bool all_left = g.half == g.count;
+    const int64_t np = A.positions;
+    const uint32_t *Xin = A.X + I.P;
+    const uint32_t *x = Xin + (int64_t)ns.axis * np;
+    const int w = threadIdx.x / kWave;
+    const int lane = __lane_id();
+
+    // the median: the point of rank `half` along the axis, digit by digit
+    // (with no right half every point goes left and none is needed)
+    uint32_t prefix = 0u, rank = (uint32_t)g.half;
+    for (int pass = 0; !all_left && pass < ns.passes; ++pass) {
+        int lo, hi;
+        digit_bits(ns.bits, pass, kB, lo, hi);
+        const uint32_t dmask = (1u << (hi - lo)) - 1u;
+        for (int b = threadIdx.x; b < kBins; b += NT)
+            s_h[b] = 0u;
+        __syncthreads();
+        uint32_t xn[kItems];
+        load_items(x, end, g.start + (int64_t)w * kWaveItems, xn);
+        for (int64_t c = g.start; c < end; c += kRun) {
+            uint32_t xv[kItems];
+#pragma unroll
+            for (int r = 0; r < kItems; ++r)
+                xv[r] = xn[r];
+            if (c + kRun < end)
+                load_items(x, end, c + kRun + (int64_t)w * kWaveItems, xn);
+#pragma unroll
+            for (int r = 0; r < kItems; ++r) {
+                const int64_t e = c + (int64_t)w * kWaveItems + (int64_t)r * kWave + lane;
+                const uint64_t v = (uint64_t)(xv[r] - ns.base);
+                const bool match = e < end && (v >> hi) == (uint64_t)prefix;
+                const uint32_t dg = (uint32_t)(v >> lo) & dmask;
+                const uint64_t mm = __ballot(match);
+                const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)dg);
+                if (__ballot(match && dg != d0) == 0) {
+                    if (mm != 0 && lane == 0)
+                        atomicAdd(&s_h[d0], (uint32_t)__popcll(mm));
+                } else if (match) {
+                    atomicAdd(&s_h[dg], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t cnt[kPer], mine = 0u;
+#pragma unroll
+        for (int b = 0; b < kPer; ++b) {
+            cnt[b] = s_h[threadIdx.x * kPer + b];
+            mine += cnt[b];
+        }
+        uint32_t cum = block_incl_scan(mine, s_scan) - mine;
+#pragma unroll
+        for (int b = 0; b < kPer; ++b) {
+            if (cum <= rank && rank < cum + cnt[b]) {
+                s_pick[0] = threadIdx.x * kPer + b;
+                s_pick[1] = cum;
+            }
+            cum += cnt[b];
+        }
+        __syncthreads();
+        prefix = (prefix << (hi - lo)) | s_pick[0];
+        rank -= s_pick[1];
+        __syncthreads();  // s_pick and s_h are used again
+    }
+    const uint32_t median = prefix, need_eq = rank;
+    if (threadIdx.x == 0) {
+        const int64_t v = (1ll << j) + t;
+        split_hint[I.N + v] = ((uint64_t)(uint32_t)ns.axis << 32) | (uint64_t)(ns.base + median);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            tree_box[((I.N + v) * D + k) * 2 + 0] = (C)((int64_t)I.lo[k] + (int64_t)nb[2 * k]);
+            tree_box[((I.N + v) * D + k) * 2 + 1] = (C)((int64_t)I.lo[k] + (int64_t)nb[2 * k + 1]);
+            rel_box[((I.N + v) * D + k) * 2 + 0] = nb[2 * k];
+            rel_box[((I.N + v) * D + k) * 2 + 1] = nb[2 * k + 1];
+        }
+    }
+
+    // the stable partition, run by run
+    const uint32_t *Iin = Iin_all + I.P;
+    uint32_t *Xout = Xout_all + I.P;
+    uint32_t *Iout = Iout_all + I.P;
+    uint32_t lmin[D], lmax[D], rmin[D], rmax[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        lmin[k] = rmin[k] = 0xFFFFFFFFu;
+        lmax[k] = rmax[k] = 0u;
+    }
+    uint32_t below_run = 0u, equal_run = 0u;  // the node's points before this run below / equal to the median
+    int par = 0;
+    for (int64_t c = g.start; c < end; c += kRun, par ^= 1) {
+        const int64_t ew = c + (int64_t)w * kWaveItems;
+        uint32_t xv[D][kItems], iv[kItems];
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            load_items(Xin + (int64_t)k * np, end, ew, xv[k]);
+        load_items(Iin, end, ew, iv);
+        uint32_t lb[kItems], eb[kItems];
+        uint32_t less_bits = 0u, eq_bits = 0u, run_l = 0u, run_e = 0u;
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int64_t e = ew + (int64_t)r * kWave + lane;
+            uint32_t va = xv[0][r];
+#pragma unroll
+            for (int k = 1; k < D; ++k)
+                va = ns.axis == k ? xv[k][r] : va;
+            const uint32_t v = va - ns.base;
+            const bool less = e < end && (all_left || v < median);
+            const bool eq = e < end && !all_left && v == median;
+            const uint64_t ml = __ballot(less), me = __ballot(eq);
+            lb[r] = run_l + (uint32_t)__popcll(ml & lanes_below());
+            eb[r] = run_e + (uint32_t)__popcll(me & lanes_below());
+            run_l += (uint32_t)__popcll(ml);
+            run_e += (uint32_t)__popcll(me);
+            less_bits |= (less ? 1u : 0u) << r;
+            eq_bits |= (eq ? 1u : 0u) << r;
+        }
+        if (lane == 0) {
+            s_w[par][0][w] = run_l;
+            s_w[par][1][w] = run_e;
+        }
+        __syncthreads();
+        uint32_t off_l = below_run, off_e = equal_run;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const uint32_t a = s_w[par][0][q], b = s_w[par][1][q];
+            off_l += q < w ? a : 0u;
+            off_e += q < w ? b : 0u;
+            below_run += a;
+            equal_run += b;
+        }
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int64_t e = ew + (int64_t)r * kWave + lane;
+            if (e >= end)
+                continue;
+            const bool less = (less_bits >> r) & 1u, eq = (eq_bits >> r) & 1u;
+            const uint32_t lbefore = off_l + lb[r];
+            const uint32_t ebefore = off_e + eb[r];
+            const bool left = less || (eq && ebefore < need_eq);
+            const uint32_t eq_left_before = ebefore < need_eq ? ebefore : need_eq;
+            const int64_t left_before = (int64_t)lbefore + (int64_t)eq_left_before;
+            const int64_t pos = e - g.start;
+            const int64_t dst = left ? g.start + left_before : g.start + g.half + (pos - left_before);
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const uint32_t v = xv[k][r];
+                Xout[(int64_t)k * np + dst] = v;
+                if (left) {
+                    lmin[k] = v < lmin[k] ? v : lmin[k];
+                    lmax[k] = v > lmax[k] ? v : lmax[k];
+                } else {
+                    rmin[k] = v < rmin[k] ? v : rmin[k];
+                    rmax[k] = v > rmax[k] ? v : rmax[k];
+                }
+            }
+            Iout[dst] = iv[r];
+        }
+    }
+    // the children's boxes ([child][axis][min, max]; an empty child keeps min > max)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        group_min_max<6>(lmin[k], lmax[k]);
+        group_min_max<6>(rmin[k], rmax[k]);
+        if (lane == kWave - 1) {
+            s_box[w][2 * k] = lmin[k];
+            s_box[w][2 * k + 1] = lmax[k];
+            s_box[w][2 * D + 2 * k] = rmin[k];
+            s_box[w][2 * D + 2 * k + 1] = rmax[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 * D) {
+        const int i = threadIdx.x;
+        uint32_t v = s_box[0][i];
+        for (int q = 1; q < NW; ++q)
+            v = (i & 1) ? (s_box[q][i] > v ? s_box[q][i] : v) : (s_box[q][i] < v ? s_box[q][i] : v);
+        uint32_t *child_boxes = A.nboxes + I.B + (2ll << j) * 2 * D;
+        child_boxes[2 * t * 2 * D + i] = v;
+    }
+}
+
 __global__ void k_fill_u32(uint32_t *__restrict__ a, int64_t m, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m)
@@ -1198,14 +1420,21 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
                        np, XA, IA);
     DPC_HIP(hipGetLastError());
 
-    // host tables: histogram workgroups of every top level (groups only) and
-    // the LDS subtrees
+    // host tables: histogram workgroups and nodes of every top level (groups
+    // only; the nodes split with shared passes and those split one workgroup
+    // each apart), the largest node of the latter per level, and the LDS
+    // subtrees
     std::vector<uint32_t> hist_blocks;
-    std::vector<int64_t> hist_first(ix.max_jb + 1, 0), node_first(ix.max_jb + 1, 0);
-    std::vector<uint2> subs, nodes;
+    std::vector<int64_t> hist_first(ix.max_jb + 1, 0), node_first(ix.max_jb + 1, 0), own_first(ix.max_jb + 1, 0),
+        own_size(ix.max_jb, 0);
+    std::vector<uint2> subs, nodes, own_nodes;
     for (int j = 0; j < ix.max_jb; ++j) {
         hist_first[j] = (int64_t)hist_blocks.size();
         node_first[j] = (int64_t)nodes.size();
+        own_first[j] = (int64_t)own_nodes.size();
+        for (const Inst &I : ix.host)
+            if (j >= top_owned_from(I.height, I.lsh, I.jb) && j < I.jb)
+                own_size[j] = std::max<int64_t>(own_size[j], (int64_t)1 << (I.height - j + I.lsh));
         if (single)
             continue;
         for (int i = 0; i < ix.count; ++i) {
@@ -1213,11 +1442,12 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
             if (j >= I.jb)
                 continue;
             const int64_t S = 1ll << (I.height - j + I.lsh);
+            std::vector<uint2> &tab = j < top_owned_from(I.height, I.lsh, I.jb) ? nodes : own_nodes;
             for (int64_t t = 0; t * S < I.n; ++t)
-                nodes.push_back(make_uint2((uint32_t)i, (uint32_t)t));
+                tab.push_back(make_uint2((uint32_t)i, (uint32_t)t));
         }
         for (const Inst &I : ix.host) {
-            if (j >= I.jb)
+            if (j >= top_owned_from(I.height, I.lsh, I.jb))
                 continue;
             const int64_t node_tiles = (1ll << (I.height - j + I.lsh)) / kTile;
             const int64_t per = node_tiles < 8 ? node_tiles : 8;
@@ -1230,6 +1460,7 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
     }
     hist_first[ix.max_jb] = (int64_t)hist_blocks.size();
     node_first[ix.max_jb] = (int64_t)nodes.size();
+    own_first[ix.max_jb] = (int64_t)own_nodes.size();
     if (!single) {
         for (int i = 0; i < ix.count; ++i) {
             const Inst &I = ix.host[i];
@@ -1239,11 +1470,12 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
         }
     }
     uint32_t *d_hist_blocks = nullptr;
-    uint2 *d_subs = nullptr, *d_nodes = nullptr;
+    uint2 *d_subs = nullptr, *d_nodes = nullptr, *d_own = nullptr;
     if (!single) {
         DPC_TRY(ws.alloc(&d_hist_blocks, hist_blocks.size() + 1));
         DPC_TRY(ws.alloc(&d_subs, subs.size() + 1));
         DPC_TRY(ws.alloc(&d_nodes, nodes.size() + 1));
+        DPC_TRY(ws.alloc(&d_own, own_nodes.size() + 1));
         if (!hist_blocks.empty())
             DPC_HIP(hipMemcpyAsync(d_hist_blocks, hist_blocks.data(), hist_blocks.size() * sizeof(uint32_t),
                                    hipMemcpyHostToDevice, s));
@@ -1251,6 +1483,9 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
             DPC_HIP(hipMemcpyAsync(d_subs, subs.data(), subs.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
         if (!nodes.empty())
             DPC_HIP(hipMemcpyAsync(d_nodes, nodes.data(), nodes.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
+        if (!own_nodes.empty())
+            DPC_HIP(hipMemcpyAsync(d_own, own_nodes.data(), own_nodes.size() * sizeof(uint2), hipMemcpyHostToDevice,
+                                   s));
         DPC_HIP(hipStreamSynchronize(s));  // the host tables go out of scope
     }
 
@@ -1260,7 +1495,7 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
         int64_t nb_words = 0, hist_words = 0, sel = 0;
         for (const Inst &I : ix.host) {
             nb_words += I.jb > 0 ? (2ll << I.jb) * 2 * D : 0;
-            hist_words += hist_words_below(I.jb, I.wbits);
+            hist_words += hist_words_below(top_owned_from(I.height, I.lsh, I.jb), I.wbits);
             sel += I.jb > 0 ? 1ll << (I.jb - 1) : 0;
         }
         uint32_t *nboxes, *hist, *cnt_less, *cnt_eq, *tile_box;
@@ -1287,6 +1522,26 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
         for (int j = 0; j < ix.max_jb; ++j) {
             const int bits = level_bits(j);
             const int passes = (ix.max_wbits + bits - 1) / bits;
+            // nodes split one workgroup each (instances whose level j is that small)
+            const unsigned ogrid =
+                single ? (own_size[j] > 0 ? 1u << j : 0u) : (unsigned)(own_first[j + 1] - own_first[j]);
+            if (ogrid > 0) {
+                const uint2 *ot = single ? nullptr : d_own + own_first[j];
+                if (own_size[j] > 8192)
+                    launch((k_node_split<C, D, 512>), dim3(ogrid), dim3(512), 0, s, ix.inst, ot, A,
+                           (const uint32_t *)Iin, Xout, Iout, j, box, ix.rbox, ix.split);
+                else
+                    launch((k_node_split<C, D, 256>), dim3(ogrid), dim3(256), 0, s, ix.inst, ot, A,
+                           (const uint32_t *)Iin, Xout, Iout, j, box, ix.rbox, ix.split);
+                DPC_HIP(hipGetLastError());
+            }
+            // nodes split by the shared passes
+            const bool shared = single ? own_size[j] == 0 : node_first[j + 1] > node_first[j];
+            if (!shared) {
+                std::swap(A.X, Xout);
+                std::swap(Iin, Iout);
+                continue;
+            }
             // histogram workgroups: a table for groups; a fixed number of
             // tiles each (up to 8, never more than a node holds) for one instance
             const uint32_t *hb = nullptr;
@@ -1331,12 +1586,8 @@ dpc_status build_kd(Workspace &ws, Index &ix) {
             launch((k_box_reduce<D>), dim3(ngrid), dim3(kThreads), 0, s, ix.inst, nt, A, j,
                    (const uint32_t *)tile_box);
             DPC_HIP(hipGetLastError());
-            uint32_t *t = A.X;
-            A.X = Xout;
-            Xout = t;
-            t = Iin;
-            Iin = Iout;
-            Iout = t;
+            std::swap(A.X, Xout);
+            std::swap(Iin, Iout);
         }
     }
     const unsigned bgrid = single ? (unsigned)(1ll << ix.host[0].jb) : (unsigned)subs.size();

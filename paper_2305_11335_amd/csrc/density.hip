@@ -88,11 +88,13 @@ __device__ inline int32_t count_within(const C (&x)[D], const C *__restrict__ p,
 // The same count on a narrow leaf: q holds the query's clamped offsets from
 // the leaf corner, packed like the leaf's points.  Each dot product starts
 // from -(T + 1), so a point is within the radius exactly when the result is
-// negative, and its sign bit is the count (T < 2^30 and every clamped
-// squared distance is below 2^31, so nothing wraps).
+// negative (T < 2^30 and every clamped squared distance is below 2^31, so
+// nothing wraps).  A batch shifts its points' sign bits into one word, one
+// funnel shift per point, and counts them with one population count.
 template <int W, int kBatch, bool kStaged>
 __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint32_t *__restrict__ p, int count,
                                               int32_t T) {
+    static_assert(kBatch >= 1 && kBatch <= 32, "a batch's sign bits fit one word");
     short2_t qv[W];
 #pragma unroll
     for (int w = 0; w < W; ++w)
@@ -107,7 +109,7 @@ __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint
             const short2_t dv = qv[w] - __builtin_bit_cast(short2_t, pp[w]);
             acc = __builtin_amdgcn_sdot2(dv, dv, acc, true);
         }
-        return (int32_t)((uint32_t)acc >> 31);
+        return (uint32_t)acc;
     };
     auto batch = [&](int t) {
         uint32_t pb[kBatch][W];
@@ -116,11 +118,11 @@ __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint
 #pragma unroll
             for (int w = 0; w < W; ++w)
                 pb[b][w] = p[(t + b) * W + w];
-        int32_t c = 0;
+        uint32_t bits = point(pb[0]) >> 31;
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b)
-            c += point(pb[b]);
-        return c;
+        for (int b = 1; b < kBatch; ++b)
+            bits = __builtin_amdgcn_alignbit(bits, point(pb[b]), 31u);  // (bits << 1) | sign
+        return (int32_t)__builtin_popcount(bits);
     };
     int32_t c = 0;
     int t = 0;
@@ -133,7 +135,7 @@ __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint
             c += batch(t);
     }
     for (; t < count; ++t)
-        c += point(p + t * W);
+        c += (int32_t)(point(p + t * W) >> 31);
     return c;
 }
 

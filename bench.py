@@ -55,11 +55,16 @@ def ops_per_pair(d: int, narrow: bool) -> float:
     """VALU lane-instructions of one exact pair test (one query against one
     point) on the cheapest exact path the kernels use, counted in this
     build's gfx950 assembly: on narrow leaves, per packed word of two axes a
-    16-bit subtract and a dot product, then the sign bit and half an add3 to
-    count it (2 * ceil(d/2) + 1.5; 3.5 in 2-D); in exact doubles, d
-    subtractions, one multiply, d - 1 fused multiply-adds and about two
-    instructions to compare and keep the result (2d + 2)."""
-    return 2 * ((d + 1) // 2) + 1.5 if narrow else 2 * d + 2
+    16-bit subtract and a dot product, then the count. Up to two dimensions
+    each point's sign bit is funnel-shifted into a word and a batch of 16 is
+    counted with one population count (17 instructions per 16 points:
+    3.0625 in 2-D); from three dimensions on, batches of two take three
+    (2 * ceil(d/2) + 1.5).  In exact doubles: d subtractions, one multiply,
+    d - 1 fused multiply-adds and about two instructions to compare and keep
+    the result (2d + 2)."""
+    if not narrow:
+        return 2 * d + 2
+    return 2 * ((d + 1) // 2) + (17 / 16 if d <= 2 else 1.5)
 
 
 def alg_bytes_per_point(d: int) -> int:

@@ -116,8 +116,9 @@ __device__ inline void group_lex_min(C &s, uint32_t &l) {
 // LDS slot each, and every step tests one query per group against all
 // points at once.  Only when some point is a candidate at most as near as a
 // query's best does the group reduce to the lexicographic minimum of
-// (D^2, index) and update that query's slot.  Same result as the per-lane
-// loop.
+// (D^2, index) and update that query's slot (with one group per wave, a
+// single such point is read from its lane instead).  Same result as the
+// per-lane loop.
 template <typename C, int D, bool STATS, int LSH>
 __device__ inline void leaf_coop(const C *__restrict__ coords, const uint64_t *__restrict__ skey, int64_t start,
                                  int count, uint64_t wm, bool want, const C (&x)[D], uint64_t kq, C &best,
@@ -164,11 +165,25 @@ __device__ inline void leaf_coop(const C *__restrict__ coords, const uint64_t *_
         const bool hit = cand && s <= qb;
         const uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
         if (hm != 0) {
-            C hs = hit ? s : std::numeric_limits<C>::max();
-            uint32_t hl = hit ? (uint32_t)pk : 0u;
-            group_lex_min<LSH, C>(hs, hl);
-            const uint64_t gm = kL == kWave ? ~0ull : ((1ull << (kL % kWave)) - 1ull) << (kL * grp);
-            const bool any = (hm & gm) != 0;
+            C hs;
+            uint32_t hl;
+            bool any;
+            if (kL == kWave && __popcll(hm) == 1) {
+                // a single hit is the minimum: read it from its lane
+                const int src = __ffsll((unsigned long long)hm) - 1;
+                const uint64_t sb = __builtin_bit_cast(uint64_t, s);
+                const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sb, src);
+                const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sb >> 32), src);
+                hs = __builtin_bit_cast(C, ((uint64_t)hi << 32) | lo);
+                hl = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)pk, src);
+                any = true;
+            } else {
+                hs = hit ? s : std::numeric_limits<C>::max();
+                hl = hit ? (uint32_t)pk : 0u;
+                group_lex_min<LSH, C>(hs, hl);
+                const uint64_t gm = kL == kWave ? ~0ull : ((1ull << (kL % kWave)) - 1ull) << (kL * grp);
+                any = (hm & gm) != 0;
+            }
             if (pl == kL - 1 && live && any) {
                 const uint32_t ql = sql[rr];
                 if ((hs < qb) | ((hs == qb) & (hl > ql))) {

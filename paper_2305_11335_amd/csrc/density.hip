@@ -162,22 +162,44 @@ __device__ inline int32_t coop_count(uint64_t pm, bool partial, const P &pt, boo
                                      Q *__restrict__ slots, F within) {
     constexpr int kL = 1 << LSH, kG = kWave / kL;
     const int lane = __lane_id();
-    const int grp = lane >> LSH;
+    const int grp = kG == 1 ? 0 : lane >> LSH;  // (a constant with one group per wave)
     const int mine = __popcll(pm & ((1ull << lane) - 1ull));
+    const uint64_t hasm = __builtin_amdgcn_ballot_w64(has);
     if (partial)
         slots[mine] = mine_q;
     wave_lds_sync();
     const int nq = __popcll(pm);
     int32_t c = 0;
-    for (int r0 = 0; r0 < nq; r0 += kG) {
-        const int r = r0 + grp;
-        const bool live = r < nq;
-        const Q q = slots[live ? r : r0];
-        const uint64_t m = __builtin_amdgcn_ballot_w64(live && has && within(pt, q));
+    if constexpr (kG == 1) {
+        // one query a step: its hits go straight to the lane of that rank
+        // (other lanes may hold one too; they are cleared at the end), two
+        // queries at a time so that their tests interleave
+        int r0 = 0;
+        for (; r0 + 2 <= nq; r0 += 2) {
+            const Q qa = slots[r0], qb = slots[r0 + 1];
+            const uint64_t ma = hasm & __builtin_amdgcn_ballot_w64(within(pt, qa));
+            const uint64_t mb = hasm & __builtin_amdgcn_ballot_w64(within(pt, qb));
+            c = mine == r0 ? __popcll(ma) : c;
+            c = mine == r0 + 1 ? __popcll(mb) : c;
+        }
+        if (r0 < nq) {
+            const Q q = slots[r0];
+            const uint64_t m = hasm & __builtin_amdgcn_ballot_w64(within(pt, q));
+            c = mine == r0 ? __popcll(m) : c;
+        }
+        c = partial ? c : 0;
+    } else {
+        for (int r0 = 0; r0 < nq; r0 += kG) {
+            const int r = r0 + grp;
+            const bool live = r < nq;
+            const Q q = slots[live ? r : r0];
+            // (one ballot per condition: the test's is its comparison's lane mask)
+            const uint64_t m = hasm & __builtin_amdgcn_ballot_w64(live) & __builtin_amdgcn_ballot_w64(within(pt, q));
 #pragma unroll
-        for (int g = 0; g < kG; ++g) {
-            const int hits = __popcll((m >> (g * kL)) & (kL == 64 ? ~0ull : ((1ull << kL) - 1ull)));
-            c += (partial && mine == r0 + g) ? hits : 0;
+            for (int g = 0; g < kG; ++g) {
+                const int hits = __popcll((m >> (g * kL)) & ((1ull << kL) - 1ull));
+                c += (partial && mine == r0 + g) ? hits : 0;
+            }
         }
     }
     wave_lds_sync();  // the slots are written again at the next leaf

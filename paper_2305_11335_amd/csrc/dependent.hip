@@ -128,7 +128,7 @@ __device__ inline void leaf_coop(const C *__restrict__ coords, const uint64_t *_
     // queries per step
     constexpr int kL = 1 << LSH, kG = kWave / kL;
     const int lane = __lane_id();
-    const int grp = lane >> LSH;
+    const int grp = kG == 1 ? 0 : lane >> LSH;  // (a constant with one group per wave)
     const int pl = lane & (kL - 1);
     const bool has = pl < count;
     const int64_t pp = start + (has ? pl : 0);

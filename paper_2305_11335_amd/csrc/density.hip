@@ -142,13 +142,16 @@ __device__ inline int32_t count_within_packed(const uint32_t (&q)[W], const uint
 __device__ inline int32_t clamp_i32(int32_t v, int32_t lo, int32_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Leaves partial to at most this many lanes of a wave are counted the
-// cooperative way (measured best: 8 lanes up to 2-D, 16 up to 4-D, 32
-// above).
-constexpr int kDenCoopMax = 32;  // the most any dimension uses
+// cooperative way (measured best: 32 lanes up to 2-D; every leaf from 3-D
+// on).
 template <int D>
 constexpr int den_coop_max() {
-    return D <= 2 ? 8 : (D <= 4 ? 16 : 32);
+    return D <= 2 ? 32 : 64;
 }
+constexpr int kDenCoopMax = den_coop_max<kMaxDim>();  // the most any dimension uses
+static_assert(den_coop_max<1>() <= kDenCoopMax && den_coop_max<3>() <= kDenCoopMax &&
+                  den_coop_max<5>() <= kDenCoopMax && kDenCoopMax <= kWave,
+              "the query slots hold every cooperative query");
 
 // Count of one leaf for the lanes in pm (the leaf is partial to them), the
 // cooperative way: each group of leaf-size lanes holds the leaf's points

@@ -5,16 +5,31 @@
 // union-find.  Here every kept edge already points to a point of strictly
 // higher priority, so each tree's root is its centre and a label is found by
 // walking parent pointers up to the root.  Walks halve their path as they go
-// (a node's parent is replaced by its grandparent), so later walks are short.
-// Those writes race with other walks' reads, but every value ever stored in
-// parent[x] is an ancestor of x in the same tree, so any value read is a valid
-// step and every walk ends at the same root.
+// (a node's parent is replaced by its grandparent), and a finished walk points
+// its whole path at the root, so later walks are short.  Those writes race
+// with other walks' reads, but every value ever stored in parent[x] is an
+// ancestor of x in the same tree, so any value read is a valid step and every
+// walk ends at the same root.
 #include "dpc_internal.hpp"
 
 namespace dpc {
 namespace {
 
 constexpr int kThreads = 256;
+
+// Points the path from x0 at its root: every node on it gets the root as its
+// parent, so that later walks through the path stop there (full path
+// compression; each store is again an ancestor of its node).
+__device__ inline void compress_path(int32_t *par, int32_t x0, int32_t root, int64_t n) {
+    int32_t y = x0;
+    for (int64_t steps = 0; y != root && steps <= n; ++steps) {
+        const int32_t p = __hip_atomic_load(&par[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (p == root)
+            break;
+        __hip_atomic_store(&par[y], root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        y = p;
+    }
+}
 
 __global__ void k_flag_init(int32_t *flag) {
     if (threadIdx.x == 0)
@@ -74,6 +89,7 @@ __global__ __launch_bounds__(kThreads) void k_roots(int64_t n, const int32_t *__
         x = g;
     }
     label[i] = x;
+    compress_path(par, (int32_t)i, x, n);
 }
 
 // The same two steps for every instance of a group, on the instances' own
@@ -122,6 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_roots_group(const Inst *__restrict
         x = g;
     }
     label[i] = x;
+    compress_path(par, (int32_t)i, x, I.n);
 }
 
 // One parent array per parameter pair (blockIdx.y), with the checks of
@@ -181,6 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_roots_sweep(int64_t n, const int32
         x = g;
     }
     label[i] = x;
+    compress_path(par, (int32_t)i, x, n);
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t v) {
